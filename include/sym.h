@@ -1,0 +1,202 @@
+/*
+ * sym.h -- C ABI of an MI355X (gfx950) library for the numeric phase of
+ * decoupled sparse Cholesky: supernodal A = L L^T and sparse triangular
+ * solve L x = b with a dense or reach-set-pruned sparse right-hand side.
+ *
+ * Problem statement (Cheshmi et al., "Sympiler", 2017): A is symmetric
+ * positive definite (Section 3.2), stored as its lower triangle in
+ * compressed sparse column form (Section 1.1, CSC {n, Lp, Li, Lx}); its
+ * pattern stays fixed while its values change (Section 1.2), so the
+ * symbolic analysis runs once and the numeric phase many times (Section
+ * 4.3); the right-hand side's pattern drives the reach-set inspector of the
+ * triangular solve (Section 3, the inspection-set table).
+ *
+ * Conventions for every call:
+ *   - Indices are 0-based.  Orderings map new to old: perm[new] = old.
+ *   - Host pointers are borrowed for the duration of the call only.
+ *   - Device pointers are caller-owned buffers on the GPU that is current
+ *     when the call is made; the library never allocates device memory.
+ *     All of its device state lives in one caller-allocated workspace.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Device work is asynchronous on that stream; no call except
+ *     sym_status and sym_export_factor synchronizes with the host.
+ *   - Return value 0 is success, negative values are the SYM_E* codes.
+ *     No exception crosses the ABI.
+ *   - A handle is not thread-safe: issue its calls on one stream at a time.
+ */
+#ifndef SYM_H
+#define SYM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SYM_OK 0
+#define SYM_EINVAL (-1)     /* null pointer, n < 0, bad option value */
+#define SYM_EPATTERN (-2)   /* entry above the diagonal, row out of range, duplicate (i, j) */
+#define SYM_ENOMEM (-3)     /* host allocation failed */
+#define SYM_EHIP (-4)       /* a HIP runtime call failed */
+#define SYM_ESTATE (-5)     /* call out of order: e.g. factor before bind, solve before factor */
+#define SYM_EWORKSPACE (-6) /* workspace too small or misaligned */
+#define SYM_ESCHED (-7)     /* a device scheduler gave up waiting (internal error) */
+
+/* orderings */
+#define SYM_ORDER_ND 0      /* the library's own graph nested dissection */
+#define SYM_ORDER_NATURAL 1 /* identity */
+#define SYM_ORDER_USER 2    /* opts.perm, used exactly as given */
+
+/* factor storage precision */
+#define SYM_F64 0
+#define SYM_F32 1
+
+typedef struct sym_opts {
+    int32_t ordering;        /* SYM_ORDER_* (default SYM_ORDER_ND) */
+    const int32_t *perm;     /* host int32[n], perm[new] = old, for SYM_ORDER_USER */
+    int32_t block_width;     /* widest column block a device task handles (default 64; 16..64, multiple of 16) */
+    int32_t precision;       /* SYM_F64 (default) or SYM_F32: storage and arithmetic of L */
+    int32_t nd_leaf;         /* SYM_ORDER_ND: subgraphs up to this size are not split further (default 64) */
+    int32_t reserved[8];
+} sym_opts;
+
+typedef struct sym_plan *sym_handle;
+typedef struct sym_rhs_plan *sym_rhs;
+
+/* Fill *opts with the defaults listed above. */
+void sym_opts_default(sym_opts *opts);
+
+/*
+ * Symbolic analysis, host only (Section 3.2, Eq. (1) and the supernode rule
+ * after it; Section 3.1 for the solve).  Input: the lower triangle of A in
+ * CSC, Ap int64[n+1], Ai int32[Ap[n]] with Ai[p] >= j for p in column j;
+ * rows may be unsorted; a missing diagonal is accepted structurally.
+ * Computes the fill-reducing ordering, the elimination tree
+ * parent[j] = min{i > j : L_ij != 0}, column counts, fundamental
+ * supernodes, their row patterns, the device task blocks, level sets and
+ * descendant lists, and the map from A's entries to L's storage.
+ * opts may be NULL for defaults.  On success *out owns a new handle.
+ * Errors: SYM_EINVAL, SYM_EPATTERN, SYM_ENOMEM.
+ */
+int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts *opts,
+                sym_handle *out);
+
+/* Bytes of device workspace the handle needs (factor, solve and plan). */
+int sym_workspace(sym_handle h, size_t *bytes);
+
+/*
+ * Attach a caller-allocated device workspace of at least sym_workspace
+ * bytes, 256-byte aligned, and upload the plan into it asynchronously on
+ * `stream`.  The workspace must stay allocated until sym_destroy or the next
+ * sym_bind.  Errors: SYM_EINVAL, SYM_EWORKSPACE, SYM_EHIP.
+ */
+int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream);
+
+/*
+ * Numeric factorization P A P^T = L L^T (Section 3.2: supernodal
+ * left-looking Cholesky with dense factorization of each diagonal block and
+ * dense triangular solves for the rows below it).  Ax_dev: device
+ * double[nnz(A)] in the order of the Ai given to sym_analyze.  Asynchronous.
+ * A non-positive pivot is not an error return: it is recorded on the device
+ * and reported by sym_status.  Errors: SYM_EINVAL, SYM_ESTATE (not bound),
+ * SYM_EHIP.
+ */
+int sym_factor(sym_handle h, const double *Ax_dev, void *stream);
+
+/*
+ * Full solve A x = b, in place: bx_dev (device double[n], original
+ * ordering) holds b on entry and x = P^T L^-T L^-1 P b on exit (Section 3.1:
+ * the diagonal block of each column block is solved first, then its result
+ * is applied to the rows below it).  Errors: SYM_EINVAL, SYM_ESTATE (no
+ * factor), SYM_EHIP.
+ */
+int sym_solve(sym_handle h, double *bx_dev, void *stream);
+
+/*
+ * Forward sweep only: y = L^-1 P b.  b_dev: device double[n] in the
+ * original ordering (read only); y_dev: device double[n] in the permuted
+ * ordering of L (written).  Errors as sym_solve.
+ */
+int sym_solve_lower(sym_handle h, const double *b_dev, double *y_dev, void *stream);
+
+/*
+ * Backward sweep only, in place: x = L^-T y for y_dev in the permuted
+ * ordering of L.  Errors as sym_solve.
+ */
+int sym_solve_upper(sym_handle h, double *y_dev, void *stream);
+
+/*
+ * Reach-set inspector for one right-hand-side pattern, host only (Section
+ * 1.1, Gilbert-Peierls: Reach_L(beta) is the set of columns reachable in the
+ * dependence graph of L from beta = {i : b_i != 0}; numerical cancellation
+ * is neglected).  bi: host int32[nb], distinct positions in the original
+ * ordering.  The result is reused for every numeric solve with that
+ * pattern.  Errors: SYM_EINVAL, SYM_ENOMEM.
+ */
+int sym_rhs_analyze(sym_handle h, int64_t nb, const int32_t *bi, sym_rhs *out);
+
+/* Device workspace bytes for an RHS plan, and its asynchronous upload into
+ * a caller buffer (256-byte aligned).  Errors as sym_workspace / sym_bind. */
+int sym_rhs_workspace(sym_rhs r, size_t *bytes);
+int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream);
+
+/*
+ * Reach-pruned forward solve y = L^-1 P b for a sparse b (Section 1.1, the
+ * decoupled code: only columns in the reach set are visited).  bv_dev:
+ * device double[nb], the values at the positions given to sym_rhs_analyze.
+ * y_dev: device double[n], permuted ordering; every entry outside the reach
+ * set is written as exactly 0.  Errors: SYM_EINVAL, SYM_ESTATE, SYM_EHIP.
+ */
+int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double *y_dev,
+                           void *stream);
+
+/* Synchronize the bound stream and return the factorization status:
+ * *info = 0, or 1 + the original index of the first column whose pivot was
+ * not positive (first in elimination order).  Errors: SYM_ESTATE, SYM_EHIP. */
+int sym_status(sym_handle h, int64_t *info);
+
+/* Copy the factor into compressed sparse column form on the host, in the
+ * pattern returned by SYM_GET_LP / SYM_GET_LI (diagonal first, rows
+ * increasing).  Lx_host: double[nnz(L)].  Synchronizes the stream. */
+int sym_export_factor(sym_handle h, double *Lx_host, void *stream);
+
+/* Symbolic outputs for inspection and tests.  sym_get_size gives the element
+ * count of an array; sym_get copies it into a host buffer of that many
+ * elements of the listed type. */
+#define SYM_GET_PERM 1        /* int32[n]   perm[new] = old */
+#define SYM_GET_PARENT 2      /* int32[n]   elimination tree, permuted numbering, -1 = root */
+#define SYM_GET_COLCOUNT 3    /* int64[n]   |L_j| including the diagonal */
+#define SYM_GET_LP 4          /* int64[n+1] column pointers of L */
+#define SYM_GET_LI 5          /* int32[nnz(L)] row indices of L, diagonal first */
+#define SYM_GET_SUPER 6       /* int32[ns+1] first column of each fundamental supernode, then n */
+#define SYM_GET_SPARENT 7     /* int32[ns]  supernodal elimination tree */
+#define SYM_GET_BLOCKS 8      /* int32[nb+1] first column of each device block, then n */
+#define SYM_GET_BLEVEL 9      /* int32[nb]  level of each block (leaves 0) */
+int sym_get_size(sym_handle h, int what, int64_t *count);
+int sym_get(sym_handle h, int what, void *out);
+
+/* Reach set of an RHS plan: int32 columns (permuted numbering), increasing. */
+int sym_rhs_get(sym_rhs r, int64_t *count, int32_t *cols_or_null);
+
+/* Scalar statistics. */
+#define SYM_STAT_N 1
+#define SYM_STAT_NNZA 2
+#define SYM_STAT_NNZL 3
+#define SYM_STAT_FLOPS 4          /* sum_j |L_j|^2: multiplies, adds, divides and square roots */
+#define SYM_STAT_NSUPER 5
+#define SYM_STAT_NBLOCKS 6
+#define SYM_STAT_NLEVELS 7
+#define SYM_STAT_NPAIRS 8         /* (descendant block, target block) update pairs */
+#define SYM_STAT_PANEL_ENTRIES 9  /* stored panel entries, incl. each diagonal block's upper part */
+#define SYM_STAT_ANALYZE_MS 10
+#define SYM_STAT_SUM_ROWS 11      /* sum over blocks of their row counts */
+int sym_stat(sym_handle h, int what, double *value);
+
+void sym_destroy(sym_handle h);
+void sym_rhs_destroy(sym_rhs r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYM_H */

@@ -1,0 +1,314 @@
+"""ctypes binding for libsym.so (names follow include/sym.h).
+
+Device buffers are torch tensors on the current CUDA (HIP) device; the
+stream is torch's current stream.  The library allocates no device memory:
+the handle's workspace is a torch uint8 tensor kept alive by the Python
+object.  If the library is missing this module raises; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsym.so")
+
+SYM_ORDER_ND, SYM_ORDER_NATURAL, SYM_ORDER_USER = 0, 1, 2
+SYM_F64, SYM_F32 = 0, 1
+
+_ERRORS = {
+    -1: "SYM_EINVAL", -2: "SYM_EPATTERN", -3: "SYM_ENOMEM", -4: "SYM_EHIP",
+    -5: "SYM_ESTATE", -6: "SYM_EWORKSPACE", -7: "SYM_ESCHED",
+}
+
+GET = dict(perm=1, parent=2, colcount=3, Lp=4, Li=5, super=6, sparent=7, blocks=8, blevel=9)
+GET_DTYPE = dict(perm=np.int32, parent=np.int32, colcount=np.int64, Lp=np.int64, Li=np.int32,
+                 super=np.int32, sparent=np.int32, blocks=np.int32, blevel=np.int32)
+STAT = dict(n=1, nnzA=2, nnzL=3, flops=4, nsuper=5, nblocks=6, nlevels=7, npairs=8,
+            panel_entries=9, analyze_ms=10, sum_rows=11)
+
+
+class SymError(RuntimeError):
+    def __init__(self, call, code):
+        super().__init__(f"{call} failed: {_ERRORS.get(code, code)}")
+        self.code = code
+        self.name = _ERRORS.get(code, str(code))
+
+
+class sym_opts(ctypes.Structure):
+    _fields_ = [("ordering", ctypes.c_int32),
+                ("perm", ctypes.POINTER(ctypes.c_int32)),
+                ("block_width", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
+                ("nd_leaf", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
+           "sym_solve", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
+           "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
+           "sym_export_factor", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
+           "sym_destroy", "sym_rhs_destroy"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsym.so; raises OSError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with paper_1705_06575_amd/build.py")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    L.sym_opts_default.restype = None
+    L.sym_opts_default.argtypes = [ctypes.POINTER(sym_opts)]
+    L.sym_analyze.argtypes = [i64, vp, vp, ctypes.POINTER(sym_opts), ctypes.POINTER(vp)]
+    L.sym_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    L.sym_bind.argtypes = [vp, vp, sz, vp]
+    L.sym_factor.argtypes = [vp, vp, vp]
+    L.sym_solve.argtypes = [vp, vp, vp]
+    L.sym_solve_lower.argtypes = [vp, vp, vp, vp]
+    L.sym_solve_upper.argtypes = [vp, vp, vp]
+    L.sym_rhs_analyze.argtypes = [vp, i64, vp, ctypes.POINTER(vp)]
+    L.sym_rhs_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    L.sym_rhs_bind.argtypes = [vp, vp, sz, vp]
+    L.sym_solve_lower_sparse.argtypes = [vp, vp, vp, vp, vp]
+    L.sym_status.argtypes = [vp, ctypes.POINTER(i64)]
+    L.sym_export_factor.argtypes = [vp, vp, vp]
+    L.sym_get_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    L.sym_get.argtypes = [vp, ctypes.c_int, vp]
+    L.sym_rhs_get.argtypes = [vp, ctypes.POINTER(i64), vp]
+    L.sym_stat.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.sym_destroy.restype = None
+    L.sym_destroy.argtypes = [vp]
+    L.sym_rhs_destroy.restype = None
+    L.sym_rhs_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if f.restype is not None and name not in ("sym_opts_default", "sym_destroy", "sym_rhs_destroy"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(call, rc):
+    if rc != 0:
+        raise SymError(call, rc)
+
+
+def opts_default() -> sym_opts:
+    o = sym_opts()
+    load_library().sym_opts_default(ctypes.byref(o))
+    return o
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str, numel: int | None = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if str(t.dtype) != dtype_name:
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Analysis:
+    """Symbolic analysis of one sparsity pattern (host), plus its device
+    workspace once bound.
+
+    Ap: int64[n+1], Ai: int32[nnz] -- lower triangle of A in CSC, 0-based.
+    ordering: "nd" (the library's graph nested dissection), "natural", or
+    an int32 permutation array perm[new] = old.
+    """
+
+    def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=64):
+        L = load_library()
+        self._lib = L
+        self.n = int(n)
+        Ap = np.ascontiguousarray(Ap, dtype=np.int64)
+        Ai = np.ascontiguousarray(Ai, dtype=np.int32)
+        if Ap.size != self.n + 1:
+            raise ValueError("Ap must have n+1 entries")
+        o = opts_default()
+        self._perm_keep = None
+        if isinstance(ordering, str):
+            o.ordering = {"nd": SYM_ORDER_ND, "natural": SYM_ORDER_NATURAL}[ordering]
+        else:
+            p = np.ascontiguousarray(ordering, dtype=np.int32)
+            if p.size != self.n:
+                raise ValueError("perm must have n entries")
+            self._perm_keep = p
+            o.ordering = SYM_ORDER_USER
+            o.perm = p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        o.block_width = int(block_width)
+        o.precision = {"f64": SYM_F64, "f32": SYM_F32}[precision]
+        o.nd_leaf = int(nd_leaf)
+        self.precision = precision
+        h = ctypes.c_void_p()
+        _check("sym_analyze", L.sym_analyze(self.n, _ptr(Ap), _ptr(Ai), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.nnzA = int(Ap[-1])
+        self._ws = None
+        self._factored = False
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.sym_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- symbolic outputs
+    def get(self, what: str) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check("sym_get_size", self._lib.sym_get_size(self._h, GET[what], ctypes.byref(cnt)))
+        out = np.zeros(max(cnt.value, 1), dtype=GET_DTYPE[what])
+        _check("sym_get", self._lib.sym_get(self._h, GET[what], _ptr(out)))
+        return out[:cnt.value]
+
+    def stat(self, what: str) -> float:
+        v = ctypes.c_double()
+        _check("sym_stat", self._lib.sym_stat(self._h, STAT[what], ctypes.byref(v)))
+        return v.value
+
+    @property
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check("sym_workspace", self._lib.sym_workspace(self._h, ctypes.byref(b)))
+        return b.value
+
+    # -- device
+    def bind(self, device=None):
+        import torch
+        nbytes = max(self.workspace_bytes, 256)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                               device=device if device is not None else "cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check("sym_bind", self._lib.sym_bind(self._h, ctypes.c_void_p(aligned),
+                                              ctypes.c_size_t(nbytes + 256 - (aligned - base)),
+                                              _stream()))
+        return self
+
+    def factor(self, Ax):
+        if self._ws is None:
+            self.bind(Ax.device)
+        _check("sym_factor", self._lib.sym_factor(self._h, _dev_ptr(Ax, "torch.float64", self.nnzA),
+                                                  _stream()))
+        self._factored = True
+        return self
+
+    def status(self) -> int:
+        info = ctypes.c_int64()
+        _check("sym_status", self._lib.sym_status(self._h, ctypes.byref(info)))
+        return info.value
+
+    def solve(self, b):
+        """x = A^-1 b (b is not modified; returns a new tensor)."""
+        x = b.clone()
+        _check("sym_solve", self._lib.sym_solve(self._h, _dev_ptr(x, "torch.float64", self.n), _stream()))
+        return x
+
+    def solve_(self, bx):
+        _check("sym_solve", self._lib.sym_solve(self._h, _dev_ptr(bx, "torch.float64", self.n), _stream()))
+        return bx
+
+    def solve_lower(self, b, out=None):
+        """y = L^-1 P b, returned in L's (permuted) ordering."""
+        import torch
+        y = out if out is not None else torch.empty_like(b)
+        _check("sym_solve_lower", self._lib.sym_solve_lower(
+            self._h, _dev_ptr(b, "torch.float64", self.n), _dev_ptr(y, "torch.float64", self.n), _stream()))
+        return y
+
+    def solve_upper_(self, y):
+        """In place: y <- L^-T y (permuted ordering)."""
+        _check("sym_solve_upper", self._lib.sym_solve_upper(self._h, _dev_ptr(y, "torch.float64", self.n),
+                                                            _stream()))
+        return y
+
+    def rhs_analyze(self, bi) -> "RhsPlan":
+        return RhsPlan(self, bi)
+
+    def solve_lower_sparse(self, r: "RhsPlan", bv, out=None):
+        import torch
+        y = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=bv.device)
+        if r._ws is None:
+            r.bind(bv.device)
+        _check("sym_solve_lower_sparse", self._lib.sym_solve_lower_sparse(
+            self._h, r._r, _dev_ptr(bv, "torch.float64", r.nb), _dev_ptr(y, "torch.float64", self.n), _stream()))
+        return y
+
+    def export_factor(self) -> np.ndarray:
+        """Host copy of L's values in the CSC pattern of get('Lp'), get('Li')."""
+        nnzL = int(self.stat("nnzL"))
+        Lx = np.zeros(max(nnzL, 1))
+        _check("sym_export_factor", self._lib.sym_export_factor(self._h, _ptr(Lx), _stream()))
+        return Lx[:nnzL]
+
+
+class RhsPlan:
+    """Reach set of one right-hand-side pattern (host) and its device copy."""
+
+    def __init__(self, an: Analysis, bi):
+        self._an = an
+        self._lib = an._lib
+        bi = np.ascontiguousarray(bi, dtype=np.int32)
+        self.nb = int(bi.size)
+        r = ctypes.c_void_p()
+        _check("sym_rhs_analyze", self._lib.sym_rhs_analyze(an._h, self.nb, _ptr(bi), ctypes.byref(r)))
+        self._r = r
+        self._ws = None
+
+    def reach(self) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check("sym_rhs_get", self._lib.sym_rhs_get(self._r, ctypes.byref(cnt), None))
+        out = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        _check("sym_rhs_get", self._lib.sym_rhs_get(self._r, ctypes.byref(cnt), _ptr(out)))
+        return out[:cnt.value]
+
+    def bind(self, device=None):
+        import torch
+        b = ctypes.c_size_t()
+        _check("sym_rhs_workspace", self._lib.sym_rhs_workspace(self._r, ctypes.byref(b)))
+        self._ws = torch.empty(b.value + 256, dtype=torch.uint8,
+                               device=device if device is not None else "cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check("sym_rhs_bind", self._lib.sym_rhs_bind(self._r, ctypes.c_void_p(aligned),
+                                                      ctypes.c_size_t(b.value + 256 - (aligned - base)),
+                                                      _stream()))
+        return self
+
+    def close(self):
+        if getattr(self, "_r", None) is not None and self._r.value:
+            self._lib.sym_rhs_destroy(self._r)
+            self._r = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

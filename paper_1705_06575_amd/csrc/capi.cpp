@@ -1,0 +1,424 @@
+// capi.cpp -- the extern "C" boundary: handles, workspace layout, binding
+// and argument checks around the symbolic analysis and the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device.hpp"
+#include "plan.hpp"
+#include "sym.h"
+
+struct sym_plan {
+    sym::Plan P;
+    size_t ws_bytes = 0;
+    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_dptr = 0, off_pairs = 0, off_tasks = 0,
+           off_tasks2 = 0, off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_info = 0;
+    sym::DevicePlan D;
+    bool bound = false;
+    bool factored = false;
+    hipStream_t stream = nullptr;
+};
+
+struct sym_rhs_plan {
+    sym_plan *h = nullptr;
+    std::vector<int32_t> reach;      // permuted columns, increasing
+    std::vector<int32_t> blocks;     // touched blocks grouped by level
+    std::vector<int32_t> cstart;     // first reached local column per touched block
+    std::vector<int32_t> bpos;       // permuted positions of b's nonzeros
+    std::vector<int64_t> level_ptr;  // groups of `blocks` per nonempty level
+    size_t ws_bytes = 0, off_blocks = 0, off_cstart = 0, off_bpos = 0;
+    sym::DeviceRhs R;
+    bool bound = false;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t elem_size(const sym::Plan &P) { return P.precision == SYM_F32 ? sizeof(float) : sizeof(double); }
+
+void layout(sym_plan *h)
+{
+    const sym::Plan &P = h->P;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    h->off_Lx = take((size_t)P.panel_entries * elem_size(P));
+    h->off_blk = take(sizeof(sym::BlockDesc) * P.blk.size());
+    h->off_rows = take(sizeof(int32_t) * P.srows.size());
+    h->off_dptr = take(sizeof(int64_t) * P.dptr.size());
+    h->off_pairs = take(sizeof(sym::Pair) * P.pairs.size());
+    h->off_tasks = take(sizeof(sym::Task) * P.tasks.size());
+    h->off_tasks2 = take(sizeof(sym::Task) * P.tasks2.size());
+    h->off_lvl = take(sizeof(int32_t) * P.level_blocks.size());
+    h->off_amap = take(sizeof(int64_t) * P.amap.size());
+    h->off_perm = take(sizeof(int32_t) * P.perm.size());
+    h->off_vec = take(sizeof(double) * (size_t)P.n);
+    h->off_info = take(sizeof(int32_t) * 4);
+    h->ws_bytes = o;
+}
+
+hipError_t upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void sym_opts_default(sym_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->ordering = SYM_ORDER_ND;
+    o->perm = nullptr;
+    o->block_width = 64;
+    o->precision = SYM_F64;
+    o->nd_leaf = 64;
+}
+
+int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts *opts,
+                sym_handle *out)
+{
+    if (!out) return SYM_EINVAL;
+    *out = nullptr;
+    sym_opts o;
+    sym_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision != SYM_F64 && o.precision != SYM_F32) return SYM_EINVAL;
+    sym_plan *h = new (std::nothrow) sym_plan();
+    if (!h) return SYM_ENOMEM;
+    int rc;
+    try {
+        h->P.precision = o.precision;
+        rc = sym::analyze(n, Ap, Ai, o.ordering, o.perm, o.block_width ? o.block_width : 64,
+                          o.nd_leaf > 0 ? o.nd_leaf : 64, h->P);
+        if (rc == SYM_OK) layout(h);
+    } catch (const std::bad_alloc &) {
+        rc = SYM_ENOMEM;
+    }
+    if (rc != SYM_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SYM_OK;
+}
+
+int sym_workspace(sym_handle h, size_t *bytes)
+{
+    if (!h || !bytes) return SYM_EINVAL;
+    *bytes = h->ws_bytes;
+    return SYM_OK;
+}
+
+int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
+{
+    if (!h || (!dev_ws && h->ws_bytes)) return SYM_EINVAL;
+    if (bytes < h->ws_bytes || ((uintptr_t)dev_ws & 255)) return SYM_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)dev_ws;
+    sym::DevicePlan &D = h->D;
+    const sym::Plan &P = h->P;
+    D.Lx = base + h->off_Lx;
+    D.blk = (sym::BlockDesc *)(base + h->off_blk);
+    D.rows = (int32_t *)(base + h->off_rows);
+    D.dptr = (int64_t *)(base + h->off_dptr);
+    D.pairs = (sym::Pair *)(base + h->off_pairs);
+    D.tasks = (sym::Task *)(base + h->off_tasks);
+    D.tasks2 = (sym::Task *)(base + h->off_tasks2);
+    D.level_blocks = (int32_t *)(base + h->off_lvl);
+    D.amap = (int64_t *)(base + h->off_amap);
+    D.perm = (int32_t *)(base + h->off_perm);
+    D.vec = (double *)(base + h->off_vec);
+    D.info = (int32_t *)(base + h->off_info);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
+    if (e == hipSuccess) e = upload(D.rows, P.srows.data(), sizeof(int32_t) * P.srows.size(), s);
+    if (e == hipSuccess) e = upload(D.dptr, P.dptr.data(), sizeof(int64_t) * P.dptr.size(), s);
+    if (e == hipSuccess) e = upload(D.pairs, P.pairs.data(), sizeof(sym::Pair) * P.pairs.size(), s);
+    if (e == hipSuccess) e = upload(D.tasks, P.tasks.data(), sizeof(sym::Task) * P.tasks.size(), s);
+    if (e == hipSuccess) e = upload(D.tasks2, P.tasks2.data(), sizeof(sym::Task) * P.tasks2.size(), s);
+    if (e == hipSuccess) e = upload(D.level_blocks, P.level_blocks.data(), sizeof(int32_t) * P.level_blocks.size(), s);
+    if (e == hipSuccess) e = upload(D.amap, P.amap.data(), sizeof(int64_t) * P.amap.size(), s);
+    if (e == hipSuccess) e = upload(D.perm, P.perm.data(), sizeof(int32_t) * P.perm.size(), s);
+    if (e != hipSuccess) return SYM_EHIP;
+    h->bound = true;
+    h->factored = false;
+    h->stream = s;
+    return SYM_OK;
+}
+
+int sym_factor(sym_handle h, const double *Ax_dev, void *stream)
+{
+    if (!h || (!Ax_dev && h->P.nnzA)) return SYM_EINVAL;
+    if (!h->bound) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    if (sym::launch_factor(h->P, h->D, Ax_dev, s) != hipSuccess) return SYM_EHIP;
+    h->factored = true;
+    return SYM_OK;
+}
+
+int sym_solve_lower(sym_handle h, const double *b_dev, double *y_dev, void *stream)
+{
+    if (!h || ((!b_dev || !y_dev) && h->P.n)) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    if (b_dev == y_dev) return SYM_EINVAL;
+    if (sym::launch_perm_gather(h->P, h->D, b_dev, y_dev, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_fwd(h->P, h->D, y_dev, s) != hipSuccess) return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_solve_upper(sym_handle h, double *y_dev, void *stream)
+{
+    if (!h || (!y_dev && h->P.n)) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    if (sym::launch_bwd(h->P, h->D, y_dev, s) != hipSuccess) return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_solve(sym_handle h, double *bx_dev, void *stream)
+{
+    if (!h || (!bx_dev && h->P.n)) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    double *y = h->D.vec;
+    if (sym::launch_perm_gather(h->P, h->D, bx_dev, y, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_fwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_bwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_perm_scatter(h->P, h->D, y, bx_dev, s) != hipSuccess) return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_rhs_analyze(sym_handle h, int64_t nb, const int32_t *bi, sym_rhs *out)
+{
+    if (!h || !out || nb < 0 || (nb > 0 && !bi)) return SYM_EINVAL;
+    *out = nullptr;
+    const sym::Plan &P = h->P;
+    sym_rhs_plan *r = new (std::nothrow) sym_rhs_plan();
+    if (!r) return SYM_ENOMEM;
+    try {
+        r->h = h;
+        std::vector<char> seen((size_t)P.n, 0);
+        std::vector<int32_t> beta;
+        beta.reserve((size_t)nb);
+        for (int64_t k = 0; k < nb; ++k) {
+            int32_t i = bi[k];
+            if (i < 0 || i >= P.n || seen[i]) { delete r; return SYM_EINVAL; }
+            seen[i] = 1;
+            beta.push_back(P.pinv[i]);
+        }
+        r->bpos = beta;
+        sym::reach_etree(P, beta, r->reach);
+        // touched blocks and their first reached column, grouped by level
+        std::vector<int32_t> bfirst((size_t)P.nb, INT32_MAX);
+        std::vector<int32_t> touched;
+        for (int32_t c : r->reach) {
+            int32_t b = P.col2blk[c];
+            if (bfirst[b] == INT32_MAX) touched.push_back(b);
+            bfirst[b] = std::min(bfirst[b], c - P.blk[b].col0);
+        }
+        std::stable_sort(touched.begin(), touched.end(),
+                         [&](int32_t a, int32_t b) { return P.blevel[a] < P.blevel[b]; });
+        r->level_ptr.push_back(0);
+        int32_t cur = -1;
+        for (int32_t b : touched) {
+            if (P.blevel[b] != cur && !r->blocks.empty()) r->level_ptr.push_back((int64_t)r->blocks.size());
+            cur = P.blevel[b];
+            r->blocks.push_back(b);
+            r->cstart.push_back(bfirst[b]);
+        }
+        if (!r->blocks.empty()) r->level_ptr.push_back((int64_t)r->blocks.size());
+        size_t o = 0;
+        auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+        r->off_blocks = take(sizeof(int32_t) * r->blocks.size());
+        r->off_cstart = take(sizeof(int32_t) * r->cstart.size());
+        r->off_bpos = take(sizeof(int32_t) * r->bpos.size());
+        r->ws_bytes = std::max<size_t>(o, 256);
+    } catch (const std::bad_alloc &) {
+        delete r;
+        return SYM_ENOMEM;
+    }
+    *out = r;
+    return SYM_OK;
+}
+
+int sym_rhs_workspace(sym_rhs r, size_t *bytes)
+{
+    if (!r || !bytes) return SYM_EINVAL;
+    *bytes = r->ws_bytes;
+    return SYM_OK;
+}
+
+int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream)
+{
+    if (!r || !dev_ws) return SYM_EINVAL;
+    if (bytes < r->ws_bytes || ((uintptr_t)dev_ws & 255)) return SYM_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)dev_ws;
+    r->R.blocks = (int32_t *)(base + r->off_blocks);
+    r->R.cstart = (int32_t *)(base + r->off_cstart);
+    r->R.bpos = (int32_t *)(base + r->off_bpos);
+    hipError_t e = upload(r->R.blocks, r->blocks.data(), sizeof(int32_t) * r->blocks.size(), s);
+    if (e == hipSuccess) e = upload(r->R.cstart, r->cstart.data(), sizeof(int32_t) * r->cstart.size(), s);
+    if (e == hipSuccess) e = upload(r->R.bpos, r->bpos.data(), sizeof(int32_t) * r->bpos.size(), s);
+    if (e != hipSuccess) return SYM_EHIP;
+    r->bound = true;
+    return SYM_OK;
+}
+
+int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double *y_dev,
+                           void *stream)
+{
+    if (!h || !r || r->h != h || (!y_dev && h->P.n) || (!bv_dev && !r->bpos.empty()))
+        return SYM_EINVAL;
+    if (!h->bound || !h->factored || !r->bound) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    if (sym::launch_fwd_sparse(h->P, h->D, r->R, r->level_ptr, (int64_t)r->bpos.size(), bv_dev,
+                               y_dev, s) != hipSuccess)
+        return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_status(sym_handle h, int64_t *info)
+{
+    if (!h || !info) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return SYM_EHIP;
+    int32_t w[2];
+    if (hipMemcpy(w, h->D.info, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return SYM_EHIP;
+    if (w[1] != INT32_MAX) return SYM_ESCHED;
+    *info = w[0] == INT32_MAX ? 0 : 1 + (int64_t)h->P.perm[w[0]];
+    return SYM_OK;
+}
+
+int sym_export_factor(sym_handle h, double *Lx_host, void *stream)
+{
+    if (!h || (!Lx_host && h->P.nnzL)) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    const sym::Plan &P = h->P;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamSynchronize(s) != hipSuccess) return SYM_EHIP;
+    const size_t es = elem_size(P);
+    std::vector<char> panel;
+    try {
+        panel.resize((size_t)P.panel_entries * es);
+    } catch (const std::bad_alloc &) {
+        return SYM_ENOMEM;
+    }
+    if (!panel.empty() &&
+        hipMemcpy(panel.data(), h->D.Lx, panel.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return SYM_EHIP;
+    int64_t q = 0;
+    for (int32_t c = 0; c < P.n; ++c) {
+        const sym::BlockDesc &d = P.blk[P.col2blk[c]];
+        const int32_t lc = c - d.col0;
+        for (int32_t lr = lc; lr < d.r; ++lr) {
+            const int64_t off = d.valoff + (int64_t)lc * d.ld + lr;
+            Lx_host[q++] = P.precision == SYM_F32 ? (double)((const float *)panel.data())[off]
+                                                  : ((const double *)panel.data())[off];
+        }
+    }
+    return SYM_OK;
+}
+
+int sym_get_size(sym_handle h, int what, int64_t *count)
+{
+    if (!h || !count) return SYM_EINVAL;
+    const sym::Plan &P = h->P;
+    switch (what) {
+    case SYM_GET_PERM: case SYM_GET_PARENT: case SYM_GET_COLCOUNT: *count = P.n; break;
+    case SYM_GET_LP: *count = (int64_t)P.n + 1; break;
+    case SYM_GET_LI: *count = P.nnzL; break;
+    case SYM_GET_SUPER: *count = (int64_t)P.ns + 1; break;
+    case SYM_GET_SPARENT: *count = P.ns; break;
+    case SYM_GET_BLOCKS: *count = (int64_t)P.nb + 1; break;
+    case SYM_GET_BLEVEL: *count = P.nb; break;
+    default: return SYM_EINVAL;
+    }
+    return SYM_OK;
+}
+
+int sym_get(sym_handle h, int what, void *out)
+{
+    if (!h || !out) return SYM_EINVAL;
+    const sym::Plan &P = h->P;
+    switch (what) {
+    case SYM_GET_PERM: std::memcpy(out, P.perm.data(), sizeof(int32_t) * P.perm.size()); break;
+    case SYM_GET_PARENT: std::memcpy(out, P.parent.data(), sizeof(int32_t) * P.parent.size()); break;
+    case SYM_GET_COLCOUNT: std::memcpy(out, P.colcount.data(), sizeof(int64_t) * P.colcount.size()); break;
+    case SYM_GET_LP: {
+        int64_t *Lp = (int64_t *)out;
+        Lp[0] = 0;
+        for (int32_t j = 0; j < P.n; ++j) Lp[j + 1] = Lp[j] + P.colcount[j];
+        break;
+    }
+    case SYM_GET_LI: {
+        int32_t *Li = (int32_t *)out;
+        int64_t q = 0;
+        for (int32_t c = 0; c < P.n; ++c) {
+            const sym::BlockDesc &d = P.blk[P.col2blk[c]];
+            const int32_t lc = c - d.col0;
+            for (int32_t lr = lc; lr < d.r; ++lr) Li[q++] = P.srows[d.rowoff + lr];
+        }
+        break;
+    }
+    case SYM_GET_SUPER: std::memcpy(out, P.sptr.data(), sizeof(int32_t) * P.sptr.size()); break;
+    case SYM_GET_SPARENT: std::memcpy(out, P.sparent.data(), sizeof(int32_t) * P.sparent.size()); break;
+    case SYM_GET_BLOCKS: std::memcpy(out, P.bptr.data(), sizeof(int32_t) * P.bptr.size()); break;
+    case SYM_GET_BLEVEL: std::memcpy(out, P.blevel.data(), sizeof(int32_t) * P.blevel.size()); break;
+    default: return SYM_EINVAL;
+    }
+    return SYM_OK;
+}
+
+int sym_rhs_get(sym_rhs r, int64_t *count, int32_t *cols)
+{
+    if (!r || !count) return SYM_EINVAL;
+    *count = (int64_t)r->reach.size();
+    if (cols) std::memcpy(cols, r->reach.data(), sizeof(int32_t) * r->reach.size());
+    return SYM_OK;
+}
+
+int sym_stat(sym_handle h, int what, double *v)
+{
+    if (!h || !v) return SYM_EINVAL;
+    const sym::Plan &P = h->P;
+    switch (what) {
+    case SYM_STAT_N: *v = P.n; break;
+    case SYM_STAT_NNZA: *v = (double)P.nnzA; break;
+    case SYM_STAT_NNZL: *v = (double)P.nnzL; break;
+    case SYM_STAT_FLOPS: *v = P.flops; break;
+    case SYM_STAT_NSUPER: *v = P.ns; break;
+    case SYM_STAT_NBLOCKS: *v = P.nb; break;
+    case SYM_STAT_NLEVELS: *v = P.nlevels; break;
+    case SYM_STAT_NPAIRS: *v = (double)P.pairs.size(); break;
+    case SYM_STAT_PANEL_ENTRIES: *v = (double)P.panel_entries; break;
+    case SYM_STAT_ANALYZE_MS: *v = P.analyze_ms; break;
+    case SYM_STAT_SUM_ROWS: {
+        double s = 0;
+        for (const auto &d : P.blk) s += d.r;
+        *v = s;
+        break;
+    }
+    default: return SYM_EINVAL;
+    }
+    return SYM_OK;
+}
+
+void sym_destroy(sym_handle h) { delete h; }
+void sym_rhs_destroy(sym_rhs r) { delete r; }
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// plan.hpp -- host-side symbolic plan and the device-side view of it.
+//
+// Storage of L: each fundamental supernode s (columns [f_s, f_s + w_s), row
+// list R_s of length r_s, sorted, whose first w_s entries are the
+// supernode's own columns) owns a dense column-major panel of r_s x w_s
+// values with leading dimension r_s.  The upper triangle of the w_s x w_s
+// diagonal block is stored but never read.
+//
+// Device tasks work on column blocks: a supernode is cut into blocks of at
+// most `block_width` columns.  Block k of s covers columns
+// [f_s + k*B, f_s + min((k+1)*B, w_s)) and rows R_s[k*B ...]; its panel is
+// the sub-panel of s starting at local (row k*B, column k*B) with the same
+// leading dimension.  Cutting changes only the blocking of the arithmetic,
+// never the factor.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace sym {
+
+struct BlockDesc {      // 32 bytes, device-visible
+    int64_t valoff;     // offset of the block's panel (its local (0,0)) in L's value array
+    int64_t rowoff;     // offset of the block's first row index in the row-index array
+    int32_t col0;       // first column (permuted numbering)
+    int32_t w;          // number of columns
+    int32_t r;          // number of rows, including the w diagonal rows
+    int32_t ld;         // leading dimension of the panel (r of the supernode)
+};
+
+struct Pair {           // 16 bytes: descendant block K updates target block J
+    int32_t K;          // descendant block id
+    int32_t a0;         // first local row of K inside J's columns
+    int32_t a1;         // one past the last local row of K inside J's columns
+    int32_t pad;
+};
+
+struct Task {           // 8 bytes: one row tile of one block
+    int32_t J;
+    int32_t t;          // tile index: local rows [t*T, min((t+1)*T, r_J))
+};
+
+constexpr int kTileRows = 64;   // T: rows per factor task tile
+
+struct Plan {
+    // ---- input
+    int32_t n = 0;
+    int64_t nnzA = 0;
+    int32_t B = 64;             // block width
+    int32_t precision = 0;      // 0 = f64, 1 = f32
+    double analyze_ms = 0.0;
+
+    // ---- ordering and column structure (permuted numbering)
+    std::vector<int32_t> perm, pinv;
+    std::vector<int32_t> parent;
+    std::vector<int64_t> colcount;
+    double flops = 0.0;         // sum_j colcount_j^2
+    int64_t nnzL = 0;
+
+    // ---- fundamental supernodes
+    int32_t ns = 0;
+    std::vector<int32_t> sptr;      // ns+1
+    std::vector<int32_t> sparent;   // ns
+    std::vector<int64_t> srowptr;   // ns+1
+    std::vector<int32_t> srows;     // sum r_s
+    std::vector<int64_t> svaloff;   // ns+1, panel offsets
+    int64_t panel_entries = 0;
+
+    // ---- device blocks
+    int32_t nb = 0;
+    std::vector<BlockDesc> blk;
+    std::vector<int32_t> bptr;      // nb+1 first column of each block, then n
+    std::vector<int32_t> bparent;   // nb
+    std::vector<int32_t> blevel;    // nb
+    std::vector<int32_t> col2blk;   // n
+    int32_t nlevels = 0;
+    std::vector<int32_t> level_ptr;     // nlevels+1 into level_blocks
+    std::vector<int32_t> level_blocks;  // nb, blocks sorted by level (stable in id)
+
+    // descendant pairs, grouped by target block
+    std::vector<int64_t> dptr;      // nb+1
+    std::vector<Pair> pairs;
+    // the same pairs grouped by descendant block (for the backward sweep)
+    std::vector<int64_t> tptr;      // nb+1
+    std::vector<int32_t> tJ;        // target block of each pair, grouped by K
+
+    // factor tasks per level
+    std::vector<int64_t> task_ptr;  // nlevels+1 : all tiles of the level's blocks
+    std::vector<Task> tasks;
+    std::vector<int64_t> task2_ptr; // nlevels+1 : row tiles t >= 1 (multi-tile blocks only)
+    std::vector<Task> tasks2;
+
+    // A -> L map (offset into L's values for every entry of A, input order)
+    std::vector<int64_t> amap;
+};
+
+// Analysis entry point (symbolic.cpp).  Returns SYM_OK or a SYM_E* code.
+int analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, int ordering,
+            const int32_t *user_perm, int block_width, int nd_leaf, Plan &P);
+
+// Graph nested dissection on the symmetric pattern (ordering.cpp).
+// adj: CSR adjacency without self loops.  Returns perm[new] = old.
+void nested_dissection(int32_t n, const std::vector<int64_t> &xadj,
+                       const std::vector<int32_t> &adj, int32_t leaf,
+                       std::vector<int32_t> &perm);
+
+// Reach set of beta (permuted numbering) in the dependence graph of L,
+// using the fact that L's column patterns are cliques of the filled graph:
+// Reach_L(beta) is the union of the elimination-tree paths from beta to the
+// roots.  Output: increasing order.
+void reach_etree(const Plan &P, const std::vector<int32_t> &beta, std::vector<int32_t> &out);
+
+}  // namespace sym

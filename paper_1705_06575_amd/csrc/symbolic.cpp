@@ -1,0 +1,391 @@
+// symbolic.cpp -- host symbolic analysis (the paper's symbolic inspector,
+// Section 3.2): ordering, elimination tree, column counts, fundamental
+// supernodes and their row patterns (Eq. (1) applied per supernode), device
+// column blocks, level sets, descendant lists (the prune set of the update
+// phase) and the map from A's entries into L's panels.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "plan.hpp"
+#include "sym.h"
+
+namespace sym {
+
+namespace {
+
+// Lower-triangular CSC of C = P A P^T plus, per entry, its index in A.
+struct PermutedLower {
+    std::vector<int64_t> cp;   // n+1
+    std::vector<int32_t> ci;   // rows (>= column), sorted
+    std::vector<int64_t> src;  // index of the entry in A's arrays
+};
+
+void permute_lower(int32_t n, const int64_t *Ap, const int32_t *Ai,
+                   const std::vector<int32_t> &pinv, PermutedLower &C)
+{
+    int64_t nnz = Ap[n];
+    C.cp.assign((size_t)n + 1, 0);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p) {
+            int32_t a = pinv[Ai[p]], b = pinv[j];
+            C.cp[(size_t)std::min(a, b) + 1]++;
+        }
+    for (int32_t j = 0; j < n; ++j) C.cp[j + 1] += C.cp[j];
+    C.ci.resize((size_t)nnz);
+    C.src.resize((size_t)nnz);
+    std::vector<int64_t> fill(C.cp.begin(), C.cp.end() - 1);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p) {
+            int32_t a = pinv[Ai[p]], b = pinv[j];
+            int32_t col = std::min(a, b), row = std::max(a, b);
+            int64_t q = fill[col]++;
+            C.ci[q] = row;
+            C.src[q] = p;
+        }
+    // sort rows within each column (carrying the source index)
+    std::vector<std::pair<int32_t, int64_t>> tmp;
+    for (int32_t j = 0; j < n; ++j) {
+        int64_t b = C.cp[j], e = C.cp[j + 1];
+        bool sorted = true;
+        for (int64_t q = b + 1; q < e; ++q)
+            if (C.ci[q] < C.ci[q - 1]) { sorted = false; break; }
+        if (sorted) continue;
+        tmp.clear();
+        for (int64_t q = b; q < e; ++q) tmp.emplace_back(C.ci[q], C.src[q]);
+        std::sort(tmp.begin(), tmp.end());
+        for (int64_t q = b; q < e; ++q) { C.ci[q] = tmp[q - b].first; C.src[q] = tmp[q - b].second; }
+    }
+}
+
+}  // namespace
+
+int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
+            const int32_t *user_perm, int block_width, int nd_leaf, Plan &P)
+{
+    auto t_start = std::chrono::steady_clock::now();
+    if (n64 < 0 || n64 > INT32_MAX - 1) return SYM_EINVAL;
+    if (n64 > 0 && (!Ap || !Ai)) return SYM_EINVAL;
+    const int32_t n = (int32_t)n64;
+    if (block_width < 16 || block_width > 64 || block_width % 16) return SYM_EINVAL;
+    P.n = n;
+    P.B = block_width;
+
+    // ---------------------------------------------------------- validation
+    if (n > 0 && Ap[0] != 0) return SYM_EPATTERN;
+    for (int32_t j = 0; j < n; ++j)
+        if (Ap[j + 1] < Ap[j]) return SYM_EPATTERN;
+    P.nnzA = n > 0 ? Ap[n] : 0;
+    {
+        std::vector<int32_t> mark((size_t)n, -1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p) {
+                int32_t i = Ai[p];
+                if (i < j || i >= n) return SYM_EPATTERN;
+                if (mark[i] == j) return SYM_EPATTERN;
+                mark[i] = j;
+            }
+    }
+
+    // ------------------------------------------------------------ ordering
+    P.perm.resize((size_t)n);
+    if (ordering == SYM_ORDER_USER) {
+        if (n > 0 && !user_perm) return SYM_EINVAL;
+        std::vector<char> seen((size_t)n, 0);
+        for (int32_t k = 0; k < n; ++k) {
+            int32_t v = user_perm[k];
+            if (v < 0 || v >= n || seen[v]) return SYM_EINVAL;
+            seen[v] = 1;
+            P.perm[k] = v;
+        }
+    } else if (ordering == SYM_ORDER_NATURAL) {
+        std::iota(P.perm.begin(), P.perm.end(), 0);
+    } else if (ordering == SYM_ORDER_ND) {
+        std::vector<int64_t> xadj((size_t)n + 1, 0);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p)
+                if (Ai[p] != j) { xadj[Ai[p] + 1]++; xadj[j + 1]++; }
+        for (int32_t j = 0; j < n; ++j) xadj[j + 1] += xadj[j];
+        std::vector<int32_t> adj((size_t)xadj[n]);
+        std::vector<int64_t> fill(xadj.begin(), xadj.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p)
+                if (Ai[p] != j) { adj[fill[Ai[p]]++] = j; adj[fill[j]++] = Ai[p]; }
+        nested_dissection(n, xadj, adj, std::max(nd_leaf, 1), P.perm);
+    } else {
+        return SYM_EINVAL;
+    }
+    P.pinv.resize((size_t)n);
+    for (int32_t k = 0; k < n; ++k) P.pinv[P.perm[k]] = k;
+
+    PermutedLower C;
+    permute_lower(n, Ap, Ai, P.pinv, C);
+
+    // row lists of the strict lower triangle of C: for row i, columns j < i
+    std::vector<int64_t> rp((size_t)n + 1, 0);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t p = C.cp[j]; p < C.cp[j + 1]; ++p)
+            if (C.ci[p] != j) rp[C.ci[p] + 1]++;
+    for (int32_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    std::vector<int32_t> rj((size_t)rp[n]);
+    {
+        std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = C.cp[j]; p < C.cp[j + 1]; ++p)
+                if (C.ci[p] != j) rj[fill[C.ci[p]]++] = j;
+    }
+
+    // ----------------------------------------------- elimination tree (3.2)
+    // parent[j] = min{i > j : L_ij != 0}; built row by row with path-compressed
+    // virtual ancestors: every entry C_kj (j < k) makes k an ancestor of j.
+    P.parent.assign((size_t)n, -1);
+    {
+        std::vector<int32_t> anc((size_t)n, -1);
+        for (int32_t k = 0; k < n; ++k) {
+            for (int64_t q = rp[k]; q < rp[k + 1]; ++q) {
+                int32_t i = rj[q];
+                while (i != -1 && i < k) {
+                    int32_t next = anc[i];
+                    anc[i] = k;
+                    if (next == -1) { P.parent[i] = k; break; }
+                    i = next;
+                }
+            }
+        }
+    }
+
+    // --------------------------------------- column counts by row subtrees
+    // Row k of L is the union of the tree paths from each j with C_kj != 0
+    // up to k; each visited column j gains row k.
+    P.colcount.assign((size_t)n, 1);
+    {
+        std::vector<int32_t> mark((size_t)n, -1);
+        for (int32_t k = 0; k < n; ++k) {
+            mark[k] = k;
+            for (int64_t q = rp[k]; q < rp[k + 1]; ++q) {
+                int32_t j = rj[q];
+                while (mark[j] != k) {
+                    mark[j] = k;
+                    P.colcount[j]++;
+                    j = P.parent[j];
+                }
+            }
+        }
+    }
+    P.nnzL = 0;
+    P.flops = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        P.nnzL += P.colcount[j];
+        P.flops += (double)P.colcount[j] * (double)P.colcount[j];
+    }
+
+    // ----------------------------------------------- fundamental supernodes
+    {
+        std::vector<int32_t> nchild((size_t)n, 0);
+        for (int32_t j = 0; j < n; ++j)
+            if (P.parent[j] >= 0) nchild[P.parent[j]]++;
+        P.sptr.clear();
+        for (int32_t j = 0; j < n; ++j) {
+            bool merge = j > 0 && P.parent[j - 1] == j && nchild[j] == 1 &&
+                         P.colcount[j - 1] - 1 == P.colcount[j];
+            if (!merge) P.sptr.push_back(j);
+        }
+        P.sptr.push_back(n);
+        P.ns = (int32_t)P.sptr.size() - 1;
+    }
+    const int32_t ns = P.ns;
+    std::vector<int32_t> col2sn((size_t)n);
+    for (int32_t s = 0; s < ns; ++s)
+        for (int32_t j = P.sptr[s]; j < P.sptr[s + 1]; ++j) col2sn[j] = s;
+    P.sparent.assign((size_t)ns, -1);
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t last = P.sptr[s + 1] - 1;
+        if (P.parent[last] >= 0) P.sparent[s] = col2sn[P.parent[last]];
+    }
+
+    // ------------------------- supernodal row patterns: Eq. (1) per supernode
+    // R_s = {own columns} u (rows of C in s's columns) u (R_t minus t's own
+    // columns, for every child supernode t).
+    P.srowptr.assign((size_t)ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) P.srowptr[s + 1] = P.srowptr[s] + P.colcount[P.sptr[s]];
+    P.srows.resize((size_t)P.srowptr[ns]);
+    {
+        std::vector<int32_t> chead((size_t)ns, -1), cnext((size_t)ns, -1);
+        for (int32_t s = ns - 1; s >= 0; --s)
+            if (P.sparent[s] >= 0) { cnext[s] = chead[P.sparent[s]]; chead[P.sparent[s]] = s; }
+        std::vector<int32_t> mark((size_t)n, -1);
+        std::vector<int32_t> buf;
+        for (int32_t s = 0; s < ns; ++s) {
+            int32_t f = P.sptr[s], l = P.sptr[s + 1] - 1;
+            buf.clear();
+            for (int32_t j = f; j <= l; ++j) mark[j] = s;
+            for (int32_t j = f; j <= l; ++j)
+                for (int64_t p = C.cp[j]; p < C.cp[j + 1]; ++p) {
+                    int32_t i = C.ci[p];
+                    if (mark[i] != s) { mark[i] = s; buf.push_back(i); }
+                }
+            for (int32_t t = chead[s]; t != -1; t = cnext[t]) {
+                int32_t wt = P.sptr[t + 1] - P.sptr[t];
+                for (int64_t p = P.srowptr[t] + wt; p < P.srowptr[t + 1]; ++p) {
+                    int32_t i = P.srows[p];
+                    if (i > l && mark[i] != s) { mark[i] = s; buf.push_back(i); }
+                }
+            }
+            std::sort(buf.begin(), buf.end());
+            int64_t need = P.srowptr[s + 1] - P.srowptr[s];
+            if ((int64_t)buf.size() + (l - f + 1) != need) return SYM_EPATTERN;  // internal inconsistency
+            int64_t o = P.srowptr[s];
+            for (int32_t j = f; j <= l; ++j) P.srows[o++] = j;
+            for (int32_t i : buf) P.srows[o++] = i;
+        }
+    }
+    P.svaloff.assign((size_t)ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t w = P.sptr[s + 1] - P.sptr[s];
+        int64_t r = P.srowptr[s + 1] - P.srowptr[s];
+        P.svaloff[s + 1] = P.svaloff[s] + w * r;
+    }
+    P.panel_entries = P.svaloff[ns];
+
+    // ------------------------------------------------------- device blocks
+    const int32_t B = P.B;
+    P.blk.clear();
+    P.bptr.clear();
+    P.col2blk.resize((size_t)n);
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t f = P.sptr[s], w = P.sptr[s + 1] - f;
+        int32_t r = (int32_t)(P.srowptr[s + 1] - P.srowptr[s]);
+        for (int32_t k = 0; k * B < w; ++k) {
+            BlockDesc d;
+            d.col0 = f + k * B;
+            d.w = std::min(B, w - k * B);
+            d.r = r - k * B;
+            d.ld = r;
+            d.rowoff = P.srowptr[s] + (int64_t)k * B;
+            d.valoff = P.svaloff[s] + (int64_t)k * B * r + (int64_t)k * B;
+            int32_t id = (int32_t)P.blk.size();
+            for (int32_t j = d.col0; j < d.col0 + d.w; ++j) P.col2blk[j] = id;
+            P.blk.push_back(d);
+            P.bptr.push_back(d.col0);
+        }
+    }
+    P.bptr.push_back(n);
+    P.nb = (int32_t)P.blk.size();
+    const int32_t nb = P.nb;
+    P.bparent.assign((size_t)nb, -1);
+    for (int32_t b = 0; b < nb; ++b) {
+        const BlockDesc &d = P.blk[b];
+        if (d.r > d.w) P.bparent[b] = P.col2blk[P.srows[d.rowoff + d.w]];
+    }
+    P.blevel.assign((size_t)nb, 0);
+    for (int32_t b = 0; b < nb; ++b)
+        if (P.bparent[b] >= 0)
+            P.blevel[P.bparent[b]] = std::max(P.blevel[P.bparent[b]], P.blevel[b] + 1);
+    P.nlevels = 0;
+    for (int32_t b = 0; b < nb; ++b) P.nlevels = std::max(P.nlevels, P.blevel[b] + 1);
+    P.level_ptr.assign((size_t)P.nlevels + 1, 0);
+    for (int32_t b = 0; b < nb; ++b) P.level_ptr[P.blevel[b] + 1]++;
+    for (int32_t l = 0; l < P.nlevels; ++l) P.level_ptr[l + 1] += P.level_ptr[l];
+    P.level_blocks.resize((size_t)nb);
+    {
+        std::vector<int32_t> fill(P.level_ptr.begin(), P.level_ptr.end() - 1);
+        for (int32_t b = 0; b < nb; ++b) P.level_blocks[fill[P.blevel[b]]++] = b;
+    }
+
+    // ------------------------------------------ descendant pairs (prune set)
+    // Block K's rows below its own columns fall into runs of consecutive
+    // local rows that lie in one target block's columns.
+    P.dptr.assign((size_t)nb + 1, 0);
+    P.tptr.assign((size_t)nb + 1, 0);
+    for (int32_t K = 0; K < nb; ++K) {
+        const BlockDesc &d = P.blk[K];
+        const int32_t *rows = P.srows.data() + d.rowoff;
+        int32_t p = d.w;
+        while (p < d.r) {
+            int32_t J = P.col2blk[rows[p]];
+            int32_t end = P.blk[J].col0 + P.blk[J].w;
+            int32_t q = p;
+            while (q < d.r && rows[q] < end) ++q;
+            P.dptr[J + 1]++;
+            P.tptr[K + 1]++;
+            p = q;
+        }
+    }
+    for (int32_t b = 0; b < nb; ++b) { P.dptr[b + 1] += P.dptr[b]; P.tptr[b + 1] += P.tptr[b]; }
+    P.pairs.resize((size_t)P.dptr[nb]);
+    P.tJ.resize((size_t)P.tptr[nb]);
+    {
+        std::vector<int64_t> fill(P.dptr.begin(), P.dptr.end() - 1);
+        int64_t tq = 0;
+        for (int32_t K = 0; K < nb; ++K) {
+            const BlockDesc &d = P.blk[K];
+            const int32_t *rows = P.srows.data() + d.rowoff;
+            int32_t p = d.w;
+            while (p < d.r) {
+                int32_t J = P.col2blk[rows[p]];
+                int32_t end = P.blk[J].col0 + P.blk[J].w;
+                int32_t q = p;
+                while (q < d.r && rows[q] < end) ++q;
+                Pair pr;
+                pr.K = K; pr.a0 = p; pr.a1 = q; pr.pad = 0;
+                P.pairs[fill[J]++] = pr;
+                P.tJ[tq++] = J;
+                p = q;
+            }
+        }
+    }
+
+    // ----------------------------------------------------- factor tasks
+    P.task_ptr.assign((size_t)P.nlevels + 1, 0);
+    P.task2_ptr.assign((size_t)P.nlevels + 1, 0);
+    P.tasks.clear();
+    P.tasks2.clear();
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+            int32_t J = P.level_blocks[q];
+            int32_t nt = (P.blk[J].r + kTileRows - 1) / kTileRows;
+            for (int32_t t = 0; t < nt; ++t) {
+                P.tasks.push_back(Task{J, t});
+                if (t > 0) P.tasks2.push_back(Task{J, t});
+            }
+        }
+        P.task_ptr[l + 1] = (int64_t)P.tasks.size();
+        P.task2_ptr[l + 1] = (int64_t)P.tasks2.size();
+    }
+
+    // ------------------------------------------------------ A -> L map
+    P.amap.resize((size_t)P.nnzA);
+    for (int32_t c = 0; c < n; ++c) {
+        const BlockDesc &d = P.blk[P.col2blk[c]];
+        const int32_t *rows = P.srows.data() + d.rowoff;
+        int32_t lc = c - d.col0;
+        for (int64_t p = C.cp[c]; p < C.cp[c + 1]; ++p) {
+            int32_t row = C.ci[p];
+            const int32_t *it = std::lower_bound(rows, rows + d.r, row);
+            if (it == rows + d.r || *it != row) return SYM_EPATTERN;   // internal inconsistency
+            int64_t lr = it - rows;
+            P.amap[C.src[p]] = d.valoff + (int64_t)lc * d.ld + lr;
+        }
+    }
+
+    P.analyze_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return SYM_OK;
+}
+
+void reach_etree(const Plan &P, const std::vector<int32_t> &beta, std::vector<int32_t> &out)
+{
+    std::vector<char> seen((size_t)P.n, 0);
+    out.clear();
+    for (int32_t b : beta) {
+        int32_t j = b;
+        while (j >= 0 && !seen[j]) {
+            seen[j] = 1;
+            out.push_back(j);
+            j = P.parent[j];
+        }
+    }
+    std::sort(out.begin(), out.end());
+}
+
+}  // namespace sym

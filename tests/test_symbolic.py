@@ -1,0 +1,187 @@
+"""Host side of the library, on the CPU: the C ABI's exports and error
+codes, and its symbolic analysis against the oracle, bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_1705_06575_amd as S
+    S.load_library()
+    return S
+
+
+def test_exports_match_header(S):
+    hdr = open(os.path.join(ROOT, "include", "sym.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void)\s+(sym_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 20
+    lib = S.load_library()
+    for name in declared:
+        assert hasattr(lib, name), name
+    from paper_1705_06575_amd.binding import EXPORTS
+    assert set(EXPORTS) == declared
+
+
+def _check_symbolic(S, orc, w, perm):
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=perm)
+    Cp, Ci, _ = orc.permute(w.n, w.Ap, w.Ai, w.Ax, perm)
+    Lp, Li, par = orc.symbolic_eq1(w.n, Cp, Ci)
+    assert np.array_equal(an.get("perm"), np.asarray(perm, np.int32))
+    assert np.array_equal(an.get("parent"), par)
+    assert np.array_equal(an.get("colcount"), np.diff(Lp))
+    assert np.array_equal(an.get("Lp"), Lp)
+    assert np.array_equal(an.get("Li"), Li)
+    sp = orc.supernodes(w.n, par, np.diff(Lp))
+    assert np.array_equal(an.get("super"), sp)
+    assert an.stat("nnzL") == Lp[-1]
+    assert an.stat("flops") == float((np.diff(Lp).astype(float) ** 2).sum())
+    return an, Lp, Li
+
+
+def test_symbolic_matches_oracle_random(S, orc):
+    rng = np.random.default_rng(17)
+    for t in range(150):
+        n = int(rng.integers(0, 70))
+        w = W.random_spd(n, float(rng.choice([0.03, 0.1, 0.3, 0.6])), np.random.default_rng(3000 + t))
+        _check_symbolic(S, orc, w, w.perm)
+
+
+def test_symbolic_matches_bool_elim_config1(S, orc):
+    w = W.config1()
+    an, Lp, Li = _check_symbolic(S, orc, w, w.perm)
+    Cp, Ci, _ = orc.permute(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+    Lp1, Li1 = orc.bool_elim(w.n, Cp, Ci)
+    assert np.array_equal(Lp1, Lp) and np.array_equal(Li1, Li)
+
+
+@pytest.mark.parametrize("cfg", ["grid3d_7pt_16", "grid3d_27pt_12", "grid2d_9pt_40", "knn_small"])
+def test_symbolic_matches_oracle_families(S, orc, cfg):
+    if cfg == "grid3d_7pt_16":
+        w = W.config2(16)
+    elif cfg == "grid3d_27pt_12":
+        w = W.config3(12)
+    elif cfg == "grid2d_9pt_40":
+        w = W.weighted_grid((40, 40), True, 1e-2, 1e2, "shift1e-3", np.random.default_rng(1), "g")
+    else:
+        w = W.knn_instance(0, nv=1500)
+    _check_symbolic(S, orc, w, w.perm)
+
+
+def test_own_ordering_is_valid_and_consistent(S, orc):
+    """The library's own nested dissection: a permutation whose symbolic
+    analysis agrees with the oracle's on the same permutation."""
+    for w in [W.config1(), W.config2(12), W.knn_instance(1, nv=800),
+              W.random_spd(60, 0.05, np.random.default_rng(2))]:
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd")
+        p = an.get("perm")
+        assert np.array_equal(np.sort(p), np.arange(w.n))
+        an2, _, _ = _check_symbolic(S, orc, w, p)
+        assert an2.stat("nnzL") == an.stat("nnzL")
+
+
+def test_reach_matches_oracle_dfs(S, orc):
+    w = W.config1()
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm)
+    Cp, Ci, _ = orc.permute(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+    Lp, Li, _ = orc.symbolic_eq1(w.n, Cp, Ci)
+    pinv = np.empty(w.n, np.int64)
+    pinv[w.perm] = np.arange(w.n)
+    rng = np.random.default_rng(8)
+    for nb in (0, 1, 8, 100, w.n):
+        pos = np.sort(rng.choice(w.n, size=nb, replace=False)).astype(np.int32)
+        r = an.rhs_analyze(pos)
+        ref = orc.reach(w.n, Lp, Li, np.sort(pinv[pos]).astype(np.int32))
+        assert np.array_equal(r.reach(), ref)
+
+
+def _lower(n, entries):
+    entries = sorted(entries, key=lambda e: (e[1], e[0]))
+    Ap = np.zeros(n + 1, np.int64)
+    for i, j in entries:
+        Ap[j + 1] += 1
+    Ap = np.cumsum(Ap)
+    Ai = np.array([i for i, j in entries], np.int32)
+    return Ap, Ai
+
+
+def test_error_codes(S):
+    from paper_1705_06575_amd import SymError
+    # entry above the diagonal
+    Ap, Ai = _lower(3, [(0, 0), (1, 1), (2, 2)])
+    Ai_bad = Ai.copy()
+    Ai_bad[1] = 0                      # column 1 holds row 0 < 1
+    with pytest.raises(SymError) as e:
+        S.Analysis(3, Ap, Ai_bad)
+    assert e.value.name == "SYM_EPATTERN"
+    # row out of range
+    Ai_bad = Ai.copy()
+    Ai_bad[2] = 3
+    with pytest.raises(SymError) as e:
+        S.Analysis(3, Ap, Ai_bad)
+    assert e.value.name == "SYM_EPATTERN"
+    # duplicate entry
+    Ap2 = np.array([0, 2, 3, 4], np.int64)
+    Ai2 = np.array([1, 1, 1, 2], np.int32)
+    with pytest.raises(SymError) as e:
+        S.Analysis(3, Ap2, Ai2)
+    assert e.value.name == "SYM_EPATTERN"
+    # bad user permutation
+    with pytest.raises(SymError) as e:
+        S.Analysis(3, Ap, Ai, ordering=np.array([0, 0, 1], np.int32))
+    assert e.value.name == "SYM_EINVAL"
+    # bad block width
+    with pytest.raises(SymError) as e:
+        S.Analysis(3, Ap, Ai, block_width=24)
+    assert e.value.name == "SYM_EINVAL"
+    # negative n through the raw ABI
+    lib = S.load_library()
+    h = ctypes.c_void_p()
+    assert lib.sym_analyze(-1, None, None, None, ctypes.byref(h)) == -1
+    # unsorted rows and a missing diagonal are accepted
+    Ap3 = np.array([0, 2, 3, 3], np.int64)
+    Ai3 = np.array([2, 0, 2], np.int32)
+    an = S.Analysis(3, Ap3, Ai3, ordering="natural")
+    assert an.stat("nnzL") == 5
+
+
+def test_state_errors_without_device(S):
+    """Calls that need a bound workspace fail with SYM_ESTATE before any
+    device work (no GPU needed)."""
+    lib = S.load_library()
+    w = W.config1()
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm)
+    assert lib.sym_factor(an._h, ctypes.c_void_p(16), None) == -5
+    assert lib.sym_solve(an._h, ctypes.c_void_p(16), None) == -5
+    info = ctypes.c_int64()
+    assert lib.sym_status(an._h, ctypes.byref(info)) == -5
+    sz = ctypes.c_size_t()
+    assert lib.sym_workspace(an._h, ctypes.byref(sz)) == 0 and sz.value > 0
+    # misaligned workspace
+    assert lib.sym_bind(an._h, ctypes.c_void_p(4096 + 8), sz, None) == -6
+    assert lib.sym_bind(an._h, ctypes.c_void_p(4096), ctypes.c_size_t(sz.value - 1), None) == -6
+
+
+def test_empty_matrix(S):
+    an = S.Analysis(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert an.stat("nnzL") == 0 and an.stat("nblocks") == 0
+
+
+def test_block_structure(S, orc):
+    """Device blocks tile each supernode into pieces of at most B columns."""
+    for B in (16, 32, 64):
+        w = W.random_spd(150, 0.9, np.random.default_rng(4))
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, block_width=B)
+        sp = an.get("super")
+        bp = an.get("blocks")
+        assert set(sp.tolist()) <= set(bp.tolist())
+        assert (np.diff(bp) <= B).all() and bp[-1] == w.n
+        lv = an.get("blevel")
+        assert lv.max() + 1 == an.stat("nlevels")
