@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the numeric phase on one MI355X: FP64 supernodal Cholesky
+followed by the triangular solves, on the 3-D 7-point weighted Laplacian of
+a 64^3 grid (n = 262144; weights log-uniform in [0.1, 10]; diagonal = row
+sum + 1e-6), ordered by the library's own nested dissection.
+
+One step = one pass of the whole numeric path over the input already
+resident in HBM: scatter A into the supernodal panels, factor P A P^T =
+L L^T, a full solve A x = b with a dense right-hand side (permute, forward
+sweep, backward sweep, permute back) and a reach-pruned forward solve with a
+sparse right-hand side of 1% random nonzeros.
+
+Prints ONE JSON line.  `value` is the step's FP64 arithmetic (sum_j |L_j|^2
+for the factor plus 2 flops per stored entry of L per sweep) per second.
+Extra fields give each part separately; `roofline` covers the dominant
+kernel of the factor, timed with HIP events on the library's stream during
+the timed steps; `cpu_baseline` is the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+HBM_PEAK_GBPS = 8000.0       # MI355X HBM3E
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def cpu_baseline(m: int = 48):
+    """The oracle (plain C, one thread) factoring the same recipe on an m^3
+    grid with the geometric nested-dissection ordering."""
+    import oracle
+    import workloads as W
+    w = W.config2(m)
+    t0 = time.perf_counter()
+    f = oracle.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+    dt = time.perf_counter() - t0
+    return {"value": round(f["flops"] / dt / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"column Cholesky of the same 3-D 7-point recipe on a {m}^3 grid "
+                      f"(n={w.n}, {f['flops']:.3e} flops, geometric ND), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--m", type=int, default=64, help="grid side (64 = the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1705_06575_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.config2(args.m)
+    t0 = time.perf_counter()
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd")
+    analyze_s = time.perf_counter() - t0
+    an.bind(dev)
+    rng = np.random.default_rng(20260002)
+    Ax = torch.from_numpy(w.Ax).to(dev)
+    b = torch.from_numpy(W.dense_rhs(w.n, rng)).to(dev)
+    pos, val = W.sparse_rhs(w.n, w.n // 100, rng)
+    rp = an.rhs_analyze(pos).bind(dev)
+    bv = torch.from_numpy(val).to(dev)
+    x = torch.empty_like(b)
+    ys = torch.empty_like(b)
+
+    flops_factor = an.stat("flops")
+    nnzL = an.stat("nnzL")
+    reach = rp.reach()
+    colcount = an.get("colcount")
+    nnzL_reach = float(colcount[reach].sum())
+    flops_solve = 2.0 * 2.0 * nnzL            # forward + backward sweeps
+    flops_sparse = 2.0 * nnzL_reach
+    flops_step = flops_factor + flops_solve + flops_sparse
+
+    def step():
+        an.factor(Ax)
+        x.copy_(b)
+        an.solve_(x)
+        an.solve_lower_sparse(rp, bv, out=ys)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert an.status() == 0
+
+    an.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prof_ms = {k: 0.0 for k in S.Analysis.PROFILE_KINDS}
+    prof_n = {k: 0 for k in S.Analysis.PROFILE_KINDS}
+    for _ in range(args.steps):
+        step()
+        ms, n, kflops = an.profile_read()      # waits on this factor's last event only
+        for k in ms:
+            prof_ms[k] += ms[k]
+            prof_n[k] += n[k]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    an.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # parts, timed separately with events (median of the same step count)
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            e0, e1 = _events(torch)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    reps = max(3, args.steps)
+    t_factor = timed(lambda: an.factor(Ax), reps)
+    t_fwd = timed(lambda: an.solve_lower(b, out=ys), reps)
+    t_solve = timed(lambda: (x.copy_(b), an.solve_(x)), reps)
+    t_sparse = timed(lambda: an.solve_lower_sparse(rp, bv, out=ys), reps)
+
+    # SpTRSV algorithmic bytes (one forward sweep): L's values, each touched
+    # block's row indices, and 16 bytes per solved column (read + write of y)
+    blocks = an.get("blocks")
+    col2blk = np.repeat(np.arange(blocks.size - 1), np.diff(blocks))
+    rows_per_block = colcount[blocks[:-1]]
+    bytes_fwd = 8.0 * nnzL + 4.0 * float(rows_per_block.sum()) + 16.0 * w.n
+    touched = np.unique(col2blk[reach])
+    bytes_sparse = 8.0 * nnzL_reach + 4.0 * float(rows_per_block[touched].sum()) + 16.0 * reach.size
+
+    # dominant kernel of the factor, from the live events of the timed steps
+    dom = max((k for k in prof_ms if k != "scatter"), key=lambda k: prof_ms[k])
+    dom_ms_per_launch = prof_ms[dom] / max(prof_n[dom], 1)
+    dom_flops_per_launch = kflops[dom] * args.steps / max(prof_n[dom], 1)
+    achieved = dom_flops_per_launch / (dom_ms_per_launch * 1e-3) / 1e12
+
+    out = {
+        "metric": "supernodal Cholesky GFLOP/s, FP64 vs mixed+IR to 1e-12 bwd err; SpTRSV GB/s",
+        "value": round(flops_step / (ms_per_step * 1e-3) / 1e9, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"grid3d_7pt_{args.m}^3 weighted Laplacian (n={w.n}), "
+                               f"library nested dissection; factor + dense full solve + "
+                               f"1% sparse forward solve",
+                   "n": w.n, "nnz_A_lower": w.nnz, "nnz_L": int(nnzL),
+                   "factor_flops": flops_factor, "sparse_rhs_nnz": int(pos.size),
+                   "reach": int(reach.size)},
+        "factor_ms": round(t_factor, 3),
+        "factor_gflops": round(flops_factor / (t_factor * 1e-3) / 1e9, 2),
+        "factor_frac_fp64_peak": round(flops_factor / (t_factor * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "sptrsv_fwd_dense_ms": round(t_fwd, 4),
+        "sptrsv_fwd_dense_gbps": round(bytes_fwd / (t_fwd * 1e-3) / 1e9, 2),
+        "sptrsv_fwd_sparse_ms": round(t_sparse, 4),
+        "sptrsv_fwd_sparse_gbps": round(bytes_sparse / (t_sparse * 1e-3) / 1e9, 2),
+        "full_solve_ms": round(t_solve, 4),
+        "analyze_s": round(analyze_s, 3),
+        "factor_kernels_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof_ms.items()},
+        "factor_launches_per_step": {k: v // args.steps for k, v in prof_n.items()},
+        "roofline": {"kernel": f"factor {dom} update (k_{dom})", "bound": "mfma",
+                     "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -191,7 +191,25 @@ int sym_rhs_get(sym_rhs r, int64_t *count, int32_t *cols_or_null);
 #define SYM_STAT_PANEL_ENTRIES 9  /* stored panel entries, incl. each diagonal block's upper part */
 #define SYM_STAT_ANALYZE_MS 10
 #define SYM_STAT_SUM_ROWS 11      /* sum over blocks of their row counts */
+#define SYM_STAT_NPHASES 12       /* kernel launches of one factorization (excluding scatter) */
+#define SYM_STAT_NINCIDENCES 13   /* (row tile, descendant block) incidences of the factor */
+#define SYM_STAT_NSLEVELS 14      /* levels of the supernodal elimination tree */
 int sym_stat(sym_handle h, int what, double *value);
+
+/* Per-launch timing of the factorization for measurement.  With enable != 0,
+ * every later sym_factor brackets each of its kernel launches with HIP
+ * events on its stream (a small overhead).  sym_profile_read synchronizes
+ * the stream and returns, for the most recent sym_factor, the summed event
+ * time in ms and the launch count of each kernel kind:
+ *   [0] A scatter (zero fill + placement), [1] external (descendant)
+ *   updates, [2] off-diagonal triangular solves, [3] internal updates.
+ * algorithmic_flops[k] is the arithmetic each kind performs by the
+ * method's count (lower-triangle products only), from the analysis.
+ * Arrays hold SYM_PROFILE_KINDS entries.  Errors: SYM_EINVAL, SYM_ESTATE,
+ * SYM_EHIP. */
+#define SYM_PROFILE_KINDS 4
+int sym_profile(sym_handle h, int enable);
+int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algorithmic_flops);
 
 void sym_destroy(sym_handle h);
 void sym_rhs_destroy(sym_rhs r);

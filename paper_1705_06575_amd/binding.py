@@ -28,7 +28,8 @@ GET = dict(perm=1, parent=2, colcount=3, Lp=4, Li=5, super=6, sparent=7, blocks=
 GET_DTYPE = dict(perm=np.int32, parent=np.int32, colcount=np.int64, Lp=np.int64, Li=np.int32,
                  super=np.int32, sparent=np.int32, blocks=np.int32, blevel=np.int32)
 STAT = dict(n=1, nnzA=2, nnzL=3, flops=4, nsuper=5, nblocks=6, nlevels=7, npairs=8,
-            panel_entries=9, analyze_ms=10, sum_rows=11)
+            panel_entries=9, analyze_ms=10, sum_rows=11, nphases=12, nincidences=13,
+            nslevels=14)
 
 
 class SymError(RuntimeError):
@@ -51,7 +52,7 @@ EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_
            "sym_solve", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
            "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
            "sym_export_factor", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
-           "sym_destroy", "sym_rhs_destroy"]
+           "sym_profile", "sym_profile_read", "sym_destroy", "sym_rhs_destroy"]
 
 _lib = None
 
@@ -84,6 +85,8 @@ def load_library(path: str = LIB_PATH):
     L.sym_get.argtypes = [vp, ctypes.c_int, vp]
     L.sym_rhs_get.argtypes = [vp, ctypes.POINTER(i64), vp]
     L.sym_stat.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.sym_profile.argtypes = [vp, ctypes.c_int]
+    L.sym_profile_read.argtypes = [vp, vp, vp, vp]
     L.sym_destroy.restype = None
     L.sym_destroy.argtypes = [vp]
     L.sym_rhs_destroy.restype = None
@@ -260,6 +263,33 @@ class Analysis:
         _check("sym_solve_lower_sparse", self._lib.sym_solve_lower_sparse(
             self._h, r._r, _dev_ptr(bv, "torch.float64", r.nb), _dev_ptr(y, "torch.float64", self.n), _stream()))
         return y
+
+    PROFILE_KINDS = ("scatter", "external", "trsm", "internal")
+
+    def profile(self, enable: bool = True):
+        _check("sym_profile", self._lib.sym_profile(self._h, int(enable)))
+        return self
+
+    def profile_read(self):
+        """Per launch kind of the last factorization: (ms, launches,
+        algorithmic flops) dicts keyed by PROFILE_KINDS."""
+        k = len(self.PROFILE_KINDS)
+        ms = np.zeros(k)
+        n = np.zeros(k, np.int64)
+        fl = np.zeros(k)
+        _check("sym_profile_read", self._lib.sym_profile_read(self._h, _ptr(ms), _ptr(n), _ptr(fl)))
+        return ({a: float(ms[i]) for i, a in enumerate(self.PROFILE_KINDS)},
+                {a: int(n[i]) for i, a in enumerate(self.PROFILE_KINDS)},
+                {a: float(fl[i]) for i, a in enumerate(self.PROFILE_KINDS)})
+
+    def kind_flops(self):
+        """Algorithmic flops per launch kind (host-side, no GPU needed)."""
+        k = len(self.PROFILE_KINDS)
+        ms = np.zeros(k)
+        n = np.zeros(k, np.int64)
+        fl = np.zeros(k)
+        self._lib.sym_profile_read(self._h, _ptr(ms), _ptr(n), _ptr(fl))
+        return {a: float(fl[i]) for i, a in enumerate(self.PROFILE_KINDS)}
 
     def export_factor(self) -> np.ndarray:
         """Host copy of L's values in the CSC pattern of get('Lp'), get('Li')."""

@@ -15,12 +15,18 @@
 struct sym_plan {
     sym::Plan P;
     size_t ws_bytes = 0;
-    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_dptr = 0, off_pairs = 0, off_tasks = 0,
-           off_tasks2 = 0, off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_info = 0;
+    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_incs = 0,
+           off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
     bool factored = false;
     hipStream_t stream = nullptr;
+    bool profiling = false;
+    sym::FactorProfile prof;
+    ~sym_plan()
+    {
+        for (hipEvent_t e : prof.ev) (void)hipEventDestroy(e);
+    }
 };
 
 struct sym_rhs_plan {
@@ -49,10 +55,9 @@ void layout(sym_plan *h)
     h->off_Lx = take((size_t)P.panel_entries * elem_size(P));
     h->off_blk = take(sizeof(sym::BlockDesc) * P.blk.size());
     h->off_rows = take(sizeof(int32_t) * P.srows.size());
-    h->off_dptr = take(sizeof(int64_t) * P.dptr.size());
-    h->off_pairs = take(sizeof(sym::Pair) * P.pairs.size());
-    h->off_tasks = take(sizeof(sym::Task) * P.tasks.size());
-    h->off_tasks2 = take(sizeof(sym::Task) * P.tasks2.size());
+    h->off_tasks = take(sizeof(sym::Task) * P.ftasks.size());
+    h->off_iptr = take(sizeof(int64_t) * P.iptr.size());
+    h->off_incs = take(sizeof(sym::Incidence) * P.incs.size());
     h->off_lvl = take(sizeof(int32_t) * P.level_blocks.size());
     h->off_amap = take(sizeof(int64_t) * P.amap.size());
     h->off_perm = take(sizeof(int32_t) * P.perm.size());
@@ -128,10 +133,9 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.Lx = base + h->off_Lx;
     D.blk = (sym::BlockDesc *)(base + h->off_blk);
     D.rows = (int32_t *)(base + h->off_rows);
-    D.dptr = (int64_t *)(base + h->off_dptr);
-    D.pairs = (sym::Pair *)(base + h->off_pairs);
     D.tasks = (sym::Task *)(base + h->off_tasks);
-    D.tasks2 = (sym::Task *)(base + h->off_tasks2);
+    D.iptr = (int64_t *)(base + h->off_iptr);
+    D.incs = (sym::Incidence *)(base + h->off_incs);
     D.level_blocks = (int32_t *)(base + h->off_lvl);
     D.amap = (int64_t *)(base + h->off_amap);
     D.perm = (int32_t *)(base + h->off_perm);
@@ -140,10 +144,9 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.srows.data(), sizeof(int32_t) * P.srows.size(), s);
-    if (e == hipSuccess) e = upload(D.dptr, P.dptr.data(), sizeof(int64_t) * P.dptr.size(), s);
-    if (e == hipSuccess) e = upload(D.pairs, P.pairs.data(), sizeof(sym::Pair) * P.pairs.size(), s);
-    if (e == hipSuccess) e = upload(D.tasks, P.tasks.data(), sizeof(sym::Task) * P.tasks.size(), s);
-    if (e == hipSuccess) e = upload(D.tasks2, P.tasks2.data(), sizeof(sym::Task) * P.tasks2.size(), s);
+    if (e == hipSuccess) e = upload(D.tasks, P.ftasks.data(), sizeof(sym::Task) * P.ftasks.size(), s);
+    if (e == hipSuccess) e = upload(D.iptr, P.iptr.data(), sizeof(int64_t) * P.iptr.size(), s);
+    if (e == hipSuccess) e = upload(D.incs, P.incs.data(), sizeof(sym::Incidence) * P.incs.size(), s);
     if (e == hipSuccess) e = upload(D.level_blocks, P.level_blocks.data(), sizeof(int32_t) * P.level_blocks.size(), s);
     if (e == hipSuccess) e = upload(D.amap, P.amap.data(), sizeof(int64_t) * P.amap.size(), s);
     if (e == hipSuccess) e = upload(D.perm, P.perm.data(), sizeof(int32_t) * P.perm.size(), s);
@@ -160,7 +163,8 @@ int sym_factor(sym_handle h, const double *Ax_dev, void *stream)
     if (!h->bound) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     h->stream = s;
-    if (sym::launch_factor(h->P, h->D, Ax_dev, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_factor(h->P, h->D, Ax_dev, s, h->profiling ? &h->prof : nullptr) != hipSuccess)
+        return SYM_EHIP;
     h->factored = true;
     return SYM_OK;
 }
@@ -407,6 +411,9 @@ int sym_stat(sym_handle h, int what, double *v)
     case SYM_STAT_NPAIRS: *v = (double)P.pairs.size(); break;
     case SYM_STAT_PANEL_ENTRIES: *v = (double)P.panel_entries; break;
     case SYM_STAT_ANALYZE_MS: *v = P.analyze_ms; break;
+    case SYM_STAT_NPHASES: *v = (double)P.phases.size(); break;
+    case SYM_STAT_NINCIDENCES: *v = (double)P.incs.size(); break;
+    case SYM_STAT_NSLEVELS: *v = P.nslevels; break;
     case SYM_STAT_SUM_ROWS: {
         double s = 0;
         for (const auto &d : P.blk) s += d.r;
@@ -414,6 +421,42 @@ int sym_stat(sym_handle h, int what, double *v)
         break;
     }
     default: return SYM_EINVAL;
+    }
+    return SYM_OK;
+}
+
+int sym_profile(sym_handle h, int enable)
+{
+    if (!h) return SYM_EINVAL;
+    h->profiling = enable != 0;
+    if (h->profiling) {
+        const size_t need = 2 * (h->P.phases.size() + 1);
+        while (h->prof.ev.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return SYM_EHIP;
+            h->prof.ev.push_back(e);
+        }
+        h->prof.kind.assign(h->P.phases.size() + 1, 0);
+        h->prof.used = 0;
+    }
+    return SYM_OK;
+}
+
+int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algorithmic_flops)
+{
+    if (!h || !ms || !launches) return SYM_EINVAL;
+    for (int k = 0; k < SYM_PROFILE_KINDS; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+        if (algorithmic_flops) algorithmic_flops[k] = h->P.kind_flops[k];
+    }
+    if (!h->profiling || h->prof.used == 0) return SYM_ESTATE;
+    if (hipEventSynchronize(h->prof.ev[2 * h->prof.used - 1]) != hipSuccess) return SYM_EHIP;
+    for (int32_t i = 0; i < h->prof.used; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->prof.ev[2 * i], h->prof.ev[2 * i + 1]) != hipSuccess) return SYM_EHIP;
+        ms[h->prof.kind[i]] += t;
+        launches[h->prof.kind[i]] += 1;
     }
     return SYM_OK;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -14,10 +15,9 @@ struct DevicePlan {
     void *Lx = nullptr;             // panel values, double or float
     BlockDesc *blk = nullptr;       // nb
     int32_t *rows = nullptr;        // sum of supernode row counts
-    int64_t *dptr = nullptr;        // nb+1
-    Pair *pairs = nullptr;          // npairs, grouped by target
-    Task *tasks = nullptr;          // all tiles, grouped by level
-    Task *tasks2 = nullptr;         // row tiles t >= 1 of multi-tile blocks, grouped by level
+    Task *tasks = nullptr;          // factor tasks in launch order
+    int64_t *iptr = nullptr;        // tasks+1: incidence ranges of external-update tasks
+    Incidence *incs = nullptr;      // (tile, descendant) incidences
     int32_t *level_blocks = nullptr;// nb, grouped by level
     int64_t *amap = nullptr;        // nnzA
     int32_t *perm = nullptr;        // n
@@ -32,8 +32,18 @@ struct DeviceRhs {
     int32_t *bpos = nullptr;        // nb_rhs: permuted positions of b's nonzeros
 };
 
+// Optional per-launch event pairs for measurement: ev[2*i], ev[2*i+1]
+// bracket launch i; kind[i] is its launch kind (0 scatter, 1 external,
+// 2 trsm, 3 internal).
+struct FactorProfile {
+    std::vector<hipEvent_t> ev;
+    std::vector<int32_t> kind;
+    int32_t used = 0;
+};
+
 // ---- factor (factor.hip)
-hipError_t launch_factor(const Plan &P, const DevicePlan &D, const double *Ax, hipStream_t s);
+hipError_t launch_factor(const Plan &P, const DevicePlan &D, const double *Ax, hipStream_t s,
+                         FactorProfile *prof);
 
 // ---- solve (solve.hip)
 hipError_t launch_perm_gather(const Plan &P, const DevicePlan &D, const double *b, double *y,

@@ -35,9 +35,30 @@ struct Pair {           // 16 bytes: descendant block K updates target block J
     int32_t pad;
 };
 
-struct Task {           // 8 bytes: one row tile of one block
-    int32_t J;
+struct Task {           // 16 bytes: one row tile of one block
+    int32_t J;          // target block
     int32_t t;          // tile index: local rows [t*T, min((t+1)*T, r_J))
+    int32_t K;          // source block (internal updates), -1 otherwise
+    int32_t flags;      // kFuseFactor: the task also factors the block
+};
+
+// One descendant's contribution to one row tile of a target block J: K's
+// local rows [a0, a1) lie in J's columns, K's local rows [b0, b1) lie in
+// the tile's rows.
+struct Incidence {      // 24 bytes
+    int32_t K;
+    int32_t a0, a1;
+    int32_t b0, b1;
+    int32_t pad;
+};
+
+constexpr int32_t kFuseFactor = 1;
+
+// One kernel launch of the factorization.
+enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2 };
+struct Phase {
+    int32_t kind;
+    int64_t t0, t1;     // task range in Plan::ftasks
 };
 
 constexpr int kTileRows = 64;   // T: rows per factor task tile
@@ -84,11 +105,19 @@ struct Plan {
     std::vector<int64_t> tptr;      // nb+1
     std::vector<int32_t> tJ;        // target block of each pair, grouped by K
 
-    // factor tasks per level
-    std::vector<int64_t> task_ptr;  // nlevels+1 : all tiles of the level's blocks
-    std::vector<Task> tasks;
-    std::vector<int64_t> task2_ptr; // nlevels+1 : row tiles t >= 1 (multi-tile blocks only)
-    std::vector<Task> tasks2;
+    // supernodal schedule of the factorization
+    std::vector<int32_t> sbptr;     // ns+1: first block of each supernode
+    std::vector<int32_t> slevel;    // ns
+    int32_t nslevels = 0;
+    std::vector<Task> ftasks;       // all factor tasks in launch order
+    std::vector<Phase> phases;      // launches
+    std::vector<int64_t> iptr;      // ftasks.size()+1: incidences of external-update tasks
+    std::vector<Incidence> incs;
+    // arithmetic of each launch kind by the method's count (lower-triangle
+    // products, one flop per multiply, add, divide and square root):
+    // [0] scatter (none), [1] external, [2] trsm, [3] internal; the four sum
+    // to `flops`.
+    double kind_flops[4] = {0, 0, 0, 0};
 
     // A -> L map (offset into L's values for every entry of A, input order)
     std::vector<int64_t> amap;

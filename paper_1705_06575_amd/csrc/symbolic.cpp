@@ -336,22 +336,158 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         }
     }
 
-    // ----------------------------------------------------- factor tasks
-    P.task_ptr.assign((size_t)P.nlevels + 1, 0);
-    P.task2_ptr.assign((size_t)P.nlevels + 1, 0);
-    P.tasks.clear();
-    P.tasks2.clear();
-    for (int32_t l = 0; l < P.nlevels; ++l) {
-        for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
-            int32_t J = P.level_blocks[q];
-            int32_t nt = (P.blk[J].r + kTileRows - 1) / kTileRows;
-            for (int32_t t = 0; t < nt; ++t) {
-                P.tasks.push_back(Task{J, t});
-                if (t > 0) P.tasks2.push_back(Task{J, t});
+    // ------------------------------------------------ factor schedule
+    // Supernodes of one level of the supernodal elimination tree are
+    // independent.  Per level:
+    //   external: every row tile of every block of the level's supernodes
+    //             gathers its descendants from other supernodes; tile 0 of
+    //             each supernode's first block then factors that block;
+    //   trsm:     the first block's other row tiles solve against it;
+    //   for k = 1, 2, ...: internal updates of blocks c >= k by the now final
+    //             block k-1 of the same supernode (right-looking), tile 0 of
+    //             block k fused with its factorization; then block k's trsm.
+    P.sbptr.assign((size_t)ns + 1, 0);
+    for (int32_t s2 = 0; s2 < ns; ++s2) {
+        int32_t w = P.sptr[s2 + 1] - P.sptr[s2];
+        P.sbptr[s2 + 1] = P.sbptr[s2] + (w + B - 1) / B;
+    }
+    P.slevel.assign((size_t)ns, 0);
+    for (int32_t s2 = 0; s2 < ns; ++s2)
+        if (P.sparent[s2] >= 0)
+            P.slevel[P.sparent[s2]] = std::max(P.slevel[P.sparent[s2]], P.slevel[s2] + 1);
+    P.nslevels = 0;
+    for (int32_t s2 = 0; s2 < ns; ++s2) P.nslevels = std::max(P.nslevels, P.slevel[s2] + 1);
+    std::vector<int32_t> sl_ptr((size_t)P.nslevels + 1, 0), sl_list((size_t)ns);
+    for (int32_t s2 = 0; s2 < ns; ++s2) sl_ptr[P.slevel[s2] + 1]++;
+    for (int32_t l = 0; l < P.nslevels; ++l) sl_ptr[l + 1] += sl_ptr[l];
+    {
+        std::vector<int32_t> fill(sl_ptr.begin(), sl_ptr.end() - 1);
+        for (int32_t s2 = 0; s2 < ns; ++s2) sl_list[fill[P.slevel[s2]]++] = s2;
+    }
+    auto ntiles = [&](int32_t J) { return (P.blk[J].r + kTileRows - 1) / kTileRows; };
+    P.ftasks.clear();
+    P.phases.clear();
+    P.incs.clear();
+    P.iptr.assign(1, 0);
+    std::vector<std::vector<Incidence>> per_tile;
+    auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags) {
+        P.ftasks.push_back(Task{J, t, K, flags});
+        P.iptr.push_back((int64_t)P.incs.size());
+    };
+    auto open_phase = [&](int32_t kind) { P.phases.push_back(Phase{kind, (int64_t)P.ftasks.size(), 0}); };
+    auto close_phase = [&]() {
+        P.phases.back().t1 = (int64_t)P.ftasks.size();
+        if (P.phases.back().t1 == P.phases.back().t0) P.phases.pop_back();
+    };
+    for (int32_t l = 0; l < P.nslevels; ++l) {
+        int32_t maxnb = 0;
+        open_phase(kPhaseExternal);
+        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+            const int32_t s2 = sl_list[q];
+            maxnb = std::max(maxnb, P.sbptr[s2 + 1] - P.sbptr[s2]);
+            for (int32_t J = P.sbptr[s2]; J < P.sbptr[s2 + 1]; ++J) {
+                const BlockDesc &dJ = P.blk[J];
+                const int32_t *rJ = P.srows.data() + dJ.rowoff;
+                const int32_t nt = ntiles(J);
+                if ((int32_t)per_tile.size() < nt) per_tile.resize((size_t)nt);
+                for (int32_t t = 0; t < nt; ++t) per_tile[t].clear();
+                for (int64_t p = P.dptr[J]; p < P.dptr[J + 1]; ++p) {
+                    const Pair &pr = P.pairs[p];
+                    if (pr.K >= P.sbptr[s2]) break;     // internal pairs come last
+                    const BlockDesc &dK = P.blk[pr.K];
+                    const int32_t *rK = P.srows.data() + dK.rowoff;
+                    int32_t pos = pr.a0;
+                    while (pos < dK.r) {
+                        const int32_t li = (int32_t)(std::lower_bound(rJ, rJ + dJ.r, rK[pos]) - rJ);
+                        const int32_t t = li / kTileRows;
+                        const int32_t last = rJ[std::min((t + 1) * kTileRows, dJ.r) - 1];
+                        const int32_t end = (int32_t)(std::upper_bound(rK + pos, rK + dK.r, last) - rK);
+                        per_tile[t].push_back(Incidence{pr.K, pr.a0, pr.a1, pos, end, 0});
+                        pos = end;
+                    }
+                }
+                const bool first = J == P.sbptr[s2];
+                for (int32_t t = 0; t < nt; ++t) {
+                    const bool fuse = first && t == 0;
+                    if (per_tile[t].empty() && !fuse) continue;
+                    for (const Incidence &in : per_tile[t]) P.incs.push_back(in);
+                    push_task(J, t, -1, fuse ? kFuseFactor : 0);
+                }
             }
         }
-        P.task_ptr[l + 1] = (int64_t)P.tasks.size();
-        P.task2_ptr[l + 1] = (int64_t)P.tasks2.size();
+        close_phase();
+        open_phase(kPhaseTrsm);
+        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+            const int32_t J = P.sbptr[sl_list[q]];
+            for (int32_t t = 1; t < ntiles(J); ++t) push_task(J, t, -1, 0);
+        }
+        close_phase();
+        for (int32_t k = 1; k < maxnb; ++k) {
+            open_phase(kPhaseInternal);
+            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+                const int32_t s2 = sl_list[q];
+                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
+                if (nbs <= k) continue;
+                for (int32_t c = k; c < nbs; ++c)
+                    for (int32_t t = 0; t < ntiles(b0 + c); ++t)
+                        push_task(b0 + c, t, b0 + k - 1, (c == k && t == 0) ? kFuseFactor : 0);
+            }
+            close_phase();
+            open_phase(kPhaseTrsm);
+            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+                const int32_t s2 = sl_list[q];
+                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
+                if (nbs <= k) continue;
+                for (int32_t t = 1; t < ntiles(b0 + k); ++t) push_task(b0 + k, t, -1, 0);
+            }
+            close_phase();
+        }
+    }
+
+    // ----------------------------------- arithmetic per launch kind
+    {
+        auto lower_pairs = [](int64_t nrows, int64_t r0, int64_t ncols) -> double {
+            // pairs (i, j), i in [r0, r0 + nrows), j in [0, ncols), with j <= i
+            double s2 = 0;
+            for (int64_t i = r0; i < r0 + nrows; ++i) s2 += (double)std::min<int64_t>(i + 1, ncols);
+            return s2;
+        };
+        auto panel = [](int64_t nrows, int64_t r0, int64_t w) -> double {
+            // within-block work of rows [r0, r0 + nrows): sum_{j <= min(i, w-1)} (2j + 1)
+            double s2 = 0;
+            for (int64_t i = r0; i < r0 + nrows; ++i) {
+                int64_t m = std::min<int64_t>(i + 1, w);
+                s2 += (double)m * (double)m;
+            }
+            return s2;
+        };
+        for (double &f : P.kind_flops) f = 0.0;
+        for (const Phase &ph : P.phases) {
+            for (int64_t q = ph.t0; q < ph.t1; ++q) {
+                const Task &tk = P.ftasks[q];
+                const BlockDesc &J = P.blk[tk.J];
+                const int64_t r0 = (int64_t)tk.t * kTileRows;
+                const int64_t nr = std::min<int64_t>(kTileRows, J.r - r0);
+                if (ph.kind == kPhaseExternal) {
+                    for (int64_t e = P.iptr[q]; e < P.iptr[q + 1]; ++e) {
+                        const Incidence &in = P.incs[e];
+                        const int64_t nI = in.b1 - in.b0, nJ = in.a1 - in.a0;
+                        double pairs = 0;
+                        if (tk.t == 0)
+                            for (int64_t i = 0; i < nI; ++i) pairs += (double)std::min<int64_t>(i + 1, nJ);
+                        else
+                            pairs = (double)nI * (double)nJ;
+                        P.kind_flops[1] += 2.0 * P.blk[in.K].w * pairs;
+                    }
+                    if (tk.flags & kFuseFactor) P.kind_flops[1] += panel(nr, r0, J.w);
+                } else if (ph.kind == kPhaseInternal) {
+                    P.kind_flops[3] += 2.0 * P.blk[tk.K].w * lower_pairs(nr, r0, J.w);
+                    if (tk.flags & kFuseFactor) P.kind_flops[3] += panel(nr, r0, J.w);
+                } else {
+                    P.kind_flops[2] += panel(nr, r0, J.w);
+                }
+            }
+        }
     }
 
     // ------------------------------------------------------ A -> L map

@@ -185,3 +185,14 @@ def test_block_structure(S, orc):
         assert (np.diff(bp) <= B).all() and bp[-1] == w.n
         lv = an.get("blevel")
         assert lv.max() + 1 == an.stat("nlevels")
+
+
+def test_kind_flops_partition_the_method_count(S):
+    """The arithmetic attributed to the factor's launch kinds adds up to
+    sum_j |L_j|^2 exactly (a check on the schedule covering every update)."""
+    for w in [W.config1(), W.config2(20), W.random_spd(200, 1.0, np.random.default_rng(6)),
+              W.knn_instance(3, nv=1200)]:
+        for B in (16, 64):
+            an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", block_width=B)
+            kf = an.kind_flops()
+            assert sum(kf.values()) == an.stat("flops")
