@@ -58,7 +58,10 @@ typedef struct sym_opts {
     int32_t block_width;     /* widest column block a device task handles (default 64; 16..64, multiple of 16) */
     int32_t precision;       /* SYM_F64 (default) or SYM_F32: storage and arithmetic of L */
     int32_t nd_leaf;         /* SYM_ORDER_ND: subgraphs up to this size are not split further (default 64) */
-    int32_t reserved[8];
+    int32_t amalgamate;      /* 1 (default): merge small supernodes into device panels with explicit
+                                zeros; 0: device panels are the fundamental supernodes.  Reported
+                                symbolic outputs are the fundamental ones either way. */
+    int32_t reserved[7];
 } sym_opts;
 
 typedef struct sym_plan *sym_handle;
@@ -193,7 +196,9 @@ int sym_rhs_get(sym_rhs r, int64_t *count, int32_t *cols_or_null);
 #define SYM_STAT_SUM_ROWS 11      /* sum over blocks of their row counts */
 #define SYM_STAT_NPHASES 12       /* kernel launches of one factorization (excluding scatter) */
 #define SYM_STAT_NINCIDENCES 13   /* (row tile, descendant block) incidences of the factor */
-#define SYM_STAT_NSLEVELS 14      /* levels of the supernodal elimination tree */
+#define SYM_STAT_NSLEVELS 14      /* levels of the device supernodal elimination tree */
+#define SYM_STAT_NDSUPER 15       /* device supernodes (after amalgamation) */
+#define SYM_STAT_STORED_LOWER 16  /* lower-trapezoid entries stored (nnz(L) plus explicit zeros) */
 int sym_stat(sym_handle h, int what, double *value);
 
 /* Per-launch timing of the factorization for measurement.  With enable != 0,

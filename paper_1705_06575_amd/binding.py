@@ -29,7 +29,7 @@ GET_DTYPE = dict(perm=np.int32, parent=np.int32, colcount=np.int64, Lp=np.int64,
                  super=np.int32, sparent=np.int32, blocks=np.int32, blevel=np.int32)
 STAT = dict(n=1, nnzA=2, nnzL=3, flops=4, nsuper=5, nblocks=6, nlevels=7, npairs=8,
             panel_entries=9, analyze_ms=10, sum_rows=11, nphases=12, nincidences=13,
-            nslevels=14)
+            nslevels=14, ndsuper=15, stored_lower=16)
 
 
 class SymError(RuntimeError):
@@ -45,7 +45,8 @@ class sym_opts(ctypes.Structure):
                 ("block_width", ctypes.c_int32),
                 ("precision", ctypes.c_int32),
                 ("nd_leaf", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("amalgamate", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
@@ -141,7 +142,8 @@ class Analysis:
     an int32 permutation array perm[new] = old.
     """
 
-    def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=64):
+    def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=64,
+                 amalgamate=True):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -163,6 +165,7 @@ class Analysis:
         o.block_width = int(block_width)
         o.precision = {"f64": SYM_F64, "f32": SYM_F32}[precision]
         o.nd_leaf = int(nd_leaf)
+        o.amalgamate = int(bool(amalgamate))
         self.precision = precision
         h = ctypes.c_void_p()
         _check("sym_analyze", L.sym_analyze(self.n, _ptr(Ap), _ptr(Ai), ctypes.byref(o), ctypes.byref(h)))

@@ -15,7 +15,7 @@
 struct sym_plan {
     sym::Plan P;
     size_t ws_bytes = 0;
-    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_incs = 0,
+    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_incs = 0, off_imap = 0,
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -54,10 +54,11 @@ void layout(sym_plan *h)
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     h->off_Lx = take((size_t)P.panel_entries * elem_size(P));
     h->off_blk = take(sizeof(sym::BlockDesc) * P.blk.size());
-    h->off_rows = take(sizeof(int32_t) * P.srows.size());
+    h->off_rows = take(sizeof(int32_t) * P.dsrows.size());
     h->off_tasks = take(sizeof(sym::Task) * P.ftasks.size());
     h->off_iptr = take(sizeof(int64_t) * P.iptr.size());
     h->off_incs = take(sizeof(sym::Incidence) * P.incs.size());
+    h->off_imap = take(P.imap.size());
     h->off_lvl = take(sizeof(int32_t) * P.level_blocks.size());
     h->off_amap = take(sizeof(int64_t) * P.amap.size());
     h->off_perm = take(sizeof(int32_t) * P.perm.size());
@@ -85,6 +86,7 @@ void sym_opts_default(sym_opts *o)
     o->block_width = 64;
     o->precision = SYM_F64;
     o->nd_leaf = 64;
+    o->amalgamate = 1;
 }
 
 int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts *opts,
@@ -102,7 +104,7 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
     try {
         h->P.precision = o.precision;
         rc = sym::analyze(n, Ap, Ai, o.ordering, o.perm, o.block_width ? o.block_width : 64,
-                          o.nd_leaf > 0 ? o.nd_leaf : 64, h->P);
+                          o.nd_leaf > 0 ? o.nd_leaf : 64, o.amalgamate != 0, h->P);
         if (rc == SYM_OK) layout(h);
     } catch (const std::bad_alloc &) {
         rc = SYM_ENOMEM;
@@ -136,6 +138,7 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.tasks = (sym::Task *)(base + h->off_tasks);
     D.iptr = (int64_t *)(base + h->off_iptr);
     D.incs = (sym::Incidence *)(base + h->off_incs);
+    D.imap = (uint8_t *)(base + h->off_imap);
     D.level_blocks = (int32_t *)(base + h->off_lvl);
     D.amap = (int64_t *)(base + h->off_amap);
     D.perm = (int32_t *)(base + h->off_perm);
@@ -143,10 +146,11 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.info = (int32_t *)(base + h->off_info);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
-    if (e == hipSuccess) e = upload(D.rows, P.srows.data(), sizeof(int32_t) * P.srows.size(), s);
+    if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
     if (e == hipSuccess) e = upload(D.tasks, P.ftasks.data(), sizeof(sym::Task) * P.ftasks.size(), s);
     if (e == hipSuccess) e = upload(D.iptr, P.iptr.data(), sizeof(int64_t) * P.iptr.size(), s);
     if (e == hipSuccess) e = upload(D.incs, P.incs.data(), sizeof(sym::Incidence) * P.incs.size(), s);
+    if (e == hipSuccess) e = upload(D.imap, P.imap.data(), P.imap.size(), s);
     if (e == hipSuccess) e = upload(D.level_blocks, P.level_blocks.data(), sizeof(int32_t) * P.level_blocks.size(), s);
     if (e == hipSuccess) e = upload(D.amap, P.amap.data(), sizeof(int64_t) * P.amap.size(), s);
     if (e == hipSuccess) e = upload(D.perm, P.perm.data(), sizeof(int32_t) * P.perm.size(), s);
@@ -326,13 +330,19 @@ int sym_export_factor(sym_handle h, double *Lx_host, void *stream)
         hipMemcpy(panel.data(), h->D.Lx, panel.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return SYM_EHIP;
     int64_t q = 0;
-    for (int32_t c = 0; c < P.n; ++c) {
-        const sym::BlockDesc &d = P.blk[P.col2blk[c]];
-        const int32_t lc = c - d.col0;
-        for (int32_t lr = lc; lr < d.r; ++lr) {
-            const int64_t off = d.valoff + (int64_t)lc * d.ld + lr;
-            Lx_host[q++] = P.precision == SYM_F32 ? (double)((const float *)panel.data())[off]
-                                                  : ((const double *)panel.data())[off];
+    for (int32_t s = 0; s < P.ns; ++s) {
+        const int32_t *frows = P.srows.data() + P.srowptr[s];
+        const int32_t fr = (int32_t)(P.srowptr[s + 1] - P.srowptr[s]);
+        for (int32_t c = P.sptr[s]; c < P.sptr[s + 1]; ++c) {
+            const sym::BlockDesc &d = P.blk[P.col2blk[c]];
+            const int32_t *drows = P.dsrows.data() + d.rowoff;
+            const int32_t lc = c - d.col0;
+            for (int32_t p = c - P.sptr[s]; p < fr; ++p) {
+                const int32_t lr = (int32_t)(std::lower_bound(drows + lc, drows + d.r, frows[p]) - drows);
+                const int64_t off = d.valoff + (int64_t)lc * d.ld + lr;
+                Lx_host[q++] = P.precision == SYM_F32 ? (double)((const float *)panel.data())[off]
+                                                      : ((const double *)panel.data())[off];
+            }
         }
     }
     return SYM_OK;
@@ -372,10 +382,11 @@ int sym_get(sym_handle h, int what, void *out)
     case SYM_GET_LI: {
         int32_t *Li = (int32_t *)out;
         int64_t q = 0;
-        for (int32_t c = 0; c < P.n; ++c) {
-            const sym::BlockDesc &d = P.blk[P.col2blk[c]];
-            const int32_t lc = c - d.col0;
-            for (int32_t lr = lc; lr < d.r; ++lr) Li[q++] = P.srows[d.rowoff + lr];
+        for (int32_t s = 0; s < P.ns; ++s) {
+            const int32_t *frows = P.srows.data() + P.srowptr[s];
+            const int32_t fr = (int32_t)(P.srowptr[s + 1] - P.srowptr[s]);
+            for (int32_t c = P.sptr[s]; c < P.sptr[s + 1]; ++c)
+                for (int32_t p = c - P.sptr[s]; p < fr; ++p) Li[q++] = frows[p];
         }
         break;
     }
@@ -414,6 +425,17 @@ int sym_stat(sym_handle h, int what, double *v)
     case SYM_STAT_NPHASES: *v = (double)P.phases.size(); break;
     case SYM_STAT_NINCIDENCES: *v = (double)P.incs.size(); break;
     case SYM_STAT_NSLEVELS: *v = P.nslevels; break;
+    case SYM_STAT_NDSUPER: *v = P.nds; break;
+    case SYM_STAT_STORED_LOWER: {
+        double st = 0;
+        for (int32_t r = 0; r < P.nds; ++r) {
+            const double W = P.dsptr[r + 1] - P.dsptr[r];
+            const double R = (double)(P.dsrowptr[r + 1] - P.dsrowptr[r]);
+            st += W * (W + 1) / 2 + W * (R - W);
+        }
+        *v = st;
+        break;
+    }
     case SYM_STAT_SUM_ROWS: {
         double s = 0;
         for (const auto &d : P.blk) s += d.r;

@@ -18,6 +18,7 @@ struct DevicePlan {
     Task *tasks = nullptr;          // factor tasks in launch order
     int64_t *iptr = nullptr;        // tasks+1: incidence ranges of external-update tasks
     Incidence *incs = nullptr;      // (tile, descendant) incidences
+    uint8_t *imap = nullptr;        // their tile-relative rows and columns
     int32_t *level_blocks = nullptr;// nb, grouped by level
     int64_t *amap = nullptr;        // nnzA
     int32_t *perm = nullptr;        // n

@@ -88,35 +88,6 @@ __device__ __forceinline__ int wave_lower_bound(const int32_t *__restrict__ a, i
     return lo + __popcll(__ballot(less));
 }
 
-// Right-looking Cholesky of an nr x w panel held column-major in LDS
-// (stride LDC): rows [0, w) are the diagonal block, rows [w, nr) the rows
-// below it.  Each step takes the pivot's square root, divides the column
-// below it and applies the rank-1 update to the columns to its right.
-template <typename T>
-__device__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info)
-{
-    const int tid = threadIdx.x;
-    for (int k = 0; k < w; ++k) {
-        const T d = C[k * LDC + k];
-        const T l = sqrt(d);
-        __syncthreads();
-        if (tid == 0) {
-            C[k * LDC + k] = l;
-            if (!(d > T(0))) atomicMin(info, col0 + k);
-        }
-        for (int i = k + 1 + tid; i < nr; i += NT) C[k * LDC + i] /= l;
-        __syncthreads();
-        const int nc = w - k - 1;
-        const int nrow = nr - k - 1;
-        for (int idx = tid; idx < nc * nrow; idx += NT) {
-            const int c = k + 1 + idx / nrow;
-            const int i = k + 1 + idx % nrow;
-            if (i >= c) C[c * LDC + i] -= C[k * LDC + i] * C[k * LDC + c];
-        }
-        __syncthreads();
-    }
-}
-
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -172,97 +143,231 @@ __device__ __forceinline__ void wave_product(const T *__restrict__ pa, const T *
     }
 }
 
+// Value of v in lane `src` (a compile-time or wave-uniform lane index).
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+// One wavefront factors the 16-column sub-panel C[c0 : nr, c0 : c0 + wb]
+// (LDS, column-major, stride LDC) in place: lane i holds row c0 + i in
+// registers.  Column k: the pivot's square root, the division of the rows
+// below it, and the rank-1 update of the sub-panel's later columns, with the
+// needed entries of other rows read across lanes (no barriers).  Rows
+// c0 .. c0 + wb - 1 form the diagonal block (Cholesky); the rows below get
+// the triangular solve against it.
+template <typename T>
+__device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
+                                              int32_t *info)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = c0 + lane;
+    const bool mine = row < nr;
+    T r[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? C[(c0 + c) * LDC + row] : T(0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < wb) {
+            const T d = lane_value(r[k], k);
+            const T l = sqrt(d);
+            if (lane == 0 && !(d > T(0))) atomicMin(info, col0 + c0 + k);
+            if (lane == k) r[k] = l;
+            else if (lane > k) r[k] = r[k] / l;
+#pragma unroll
+            for (int c = k + 1; c < 16; ++c) {
+                if (c < wb) {
+                    const T lck = lane_value(r[k], c);
+                    if (lane >= c) r[c] -= r[k] * lck;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (mine && c < wb) C[(c0 + c) * LDC + row] = r[c];
+}
+
+// One wavefront solves X[:, c0 : c0 + wb] := X[:, c0 : c0 + wb] D^{-T} for the
+// wb x wb lower triangle D = L[c0 : c0 + wb, c0 : c0 + wb] (both LDS,
+// column-major, stride LDC), lane i owning row i of X (nr <= 64 rows).
+template <typename T>
+__device__ __forceinline__ void wave_subsolve(T *X, const T *L, int c0, int wb, int nr)
+{
+    const int lane = threadIdx.x & 63;
+    const bool mine = lane < nr;
+    T x[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) x[c] = (mine && c < wb) ? X[(c0 + c) * LDC + lane] : T(0);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        if (c < wb) {
+            T acc = x[c];
+#pragma unroll
+            for (int k = 0; k < c; ++k) acc -= x[k] * L[(c0 + k) * LDC + c0 + c];
+            x[c] = acc / L[(c0 + c) * LDC + c0 + c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (mine && c < wb) X[(c0 + c) * LDC + lane] = x[c];
+}
+
+// C[ra:nr, ca:w] -= X[ra:nr, k0:k0+kw] * Y[ca:w, k0:k0+kw]^T in 16 x 16
+// matrix-core blocks shared by the four wavefronts.  X, Y and C are LDS
+// panels (column-major, stride LDC); kw <= 16.  When rows and columns index
+// the same panel (diag_off = 0), blocks entirely above the diagonal are
+// skipped and entries above it inside a block receive harmless updates to
+// never-read storage; a diag_off of 64 or more disables the skipping.
+template <typename T>
+__device__ __forceinline__ void block_update(T *C, const T *X, const T *Y, int ra, int nr,
+                                             int ca, int w, int k0, int kw, int diag_off)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nrb = (nr - ra + 15) >> 4;
+    const int ncb = (w - ca + 15) >> 4;
+    for (int blk = wave; blk < nrb * ncb; blk += NT / 64) {
+        const int rb = ra + 16 * (blk % nrb);
+        const int cb = ca + 16 * (blk / nrb);
+        if (rb + 15 + diag_off < cb) continue;
+        typename Mfma<T>::acc_t acc = {};
+        const int ar = rb + (lane & 15);
+        const int bc = cb + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < 16; ks += 4) {
+            const int k = ks + (lane >> 4);
+            const bool vk = k < kw;
+            const T a = (vk && ar < nr) ? X[(k0 + k) * LDC + ar] : T(0);
+            const T b = (vk && bc < w) ? Y[(k0 + k) * LDC + bc] : T(0);
+            acc = Mfma<T>::mma(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = rb + Mfma<T>::row(lane, v);
+            const int c = cb + (lane & 15);
+            if (r < nr && c < w) C[c * LDC + r] -= acc[v];
+        }
+    }
+}
+
+// Cholesky of an nr x w panel (nr, w <= 64) held column-major in LDS:
+// rows [0, w) are the diagonal block, rows [w, nr) the rows below it (their
+// triangular solve is part of the same sweep).  Blocked by 16 columns: one
+// wavefront factors a sub-panel, then all four update the columns to its
+// right with matrix-core products.  Called by all threads of the workgroup.
+template <typename T>
+__device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info)
+{
+    for (int c0 = 0; c0 < w; c0 += 16) {
+        const int wb = min(16, w - c0);
+        if ((threadIdx.x >> 6) == 0) wave_subpanel(C, c0, wb, nr, col0, info);
+        __syncthreads();
+        if (c0 + wb < w) {
+            block_update(C, C, C, c0 + wb, nr, c0 + wb, w, c0, wb, 0);
+            __syncthreads();
+        }
+    }
+}
+
 // External update of one row tile of block J: for every descendant K of
-// another supernode that meets the tile, tile -= L_K[b0:b1, :] L_K[a0:a1, :]^T
-// at the relative positions of K's rows in J.  The tile stays in LDS; the
-// four wavefronts each own one 32 x 32 quadrant of every product, and
-// distinct product entries land on distinct tile entries, so no atomics are
-// needed and the summation order is fixed.  With kFuseFactor the tile is
-// tile 0 of a supernode's first block, which is then factored in place.
+// another supernode that meets the tile, tile -= L_K[b0 .. b0+nI, :] *
+// L_K[a0 .. a0+nJ, :]^T at the tile-relative rows and columns recorded by the
+// analysis.  The tile stays in LDS.  Wavefront w owns tile columns
+// [16w, 16w + 16) and walks the incidence list on its own: it skips
+// incidences whose columns miss its range, otherwise forms the product of
+// all nI rows with its (at most 16) columns on the matrix cores and
+// subtracts it from its own columns.  No two wavefronts write the same
+// entry, so the loop has no barriers and each entry is updated in list
+// order (bitwise reproducible).  The next record is fetched one iteration
+// ahead.  With kFuseFactor the tile is tile 0 of a supernode's first block,
+// which is then factored in place.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
                                                  const int64_t *__restrict__ iptr,
                                                  const Incidence *__restrict__ incs,
+                                                 const uint8_t *__restrict__ imap,
                                                  const BlockDesc *__restrict__ blk,
-                                                 const int32_t *__restrict__ rows,
                                                  T *__restrict__ Lx, int32_t *__restrict__ info)
 {
     __shared__ T C[64 * LDC];
-    __shared__ int32_t trow[TR];
-    __shared__ int32_t s_lr[TR];
-    __shared__ int32_t s_lc[64];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc J = blk[tk.J];
     const int r0 = tk.t * TR;
     const int nr = min(TR, J.r - r0);
     const int w = J.w;
-    const int32_t *rJ = rows + J.rowoff;
     T *LJ = Lx + J.valoff;
 
     for (int idx = tid; idx < nr * w; idx += NT) {
         const int i = idx % nr, c = idx / nr;
         C[c * LDC + i] = LJ[(int64_t)c * J.ld + r0 + i];
     }
-    if (tid < nr) trow[tid] = rJ[r0 + tid];
     __syncthreads();
 
+    const int c_lo = 16 * wave, c_hi = c_lo + 16;
+    int64_t q = iptr[blockIdx.x];
     const int64_t qend = iptr[blockIdx.x + 1];
-    for (int64_t q = iptr[blockIdx.x]; q < qend; ++q) {
-        const Incidence in = incs[q];
-        const BlockDesc K = blk[in.K];
-        const int32_t *rK = rows + K.rowoff;
-        const int nI = in.b1 - in.b0;
-        const int nJ = in.a1 - in.a0;
-        if (nI > nr || nJ > w || nI <= 0 || nJ <= 0) {   // corrupt plan: never write outside the tile
-            if (tid == 0) atomicMin(info + 1, tk.J);
-            continue;
-        }
-        if (tid < nI) {
-            const int key = rK[in.b0 + tid];
-            int lo = 0, hi = nr;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (trow[mid] < key) lo = mid + 1; else hi = mid;
-            }
-            if (lo >= nr || trow[lo] != key) {
-                atomicMin(info + 1, tk.J);
-                lo = 0;
-            }
-            s_lr[tid] = lo;
-        } else if (tid >= 64 && tid < 64 + nJ) {
-            int c = rK[in.a0 + tid - 64] - J.col0;
-            if (c < 0 || c >= w) {
-                atomicMin(info + 1, tk.J);
-                c = 0;
-            }
-            s_lc[tid - 64] = c;
-        }
-        __syncthreads();
-        if (32 * wr < nI && 32 * wc < nJ) {
-            typename Mfma<T>::acc_t acc[2][2] = {};
-            const T *LK = Lx + K.valoff;
-            wave_product<T>(LK + in.b0, LK + in.a0, K.ld, nI, nJ, K.w, wr, wc, T(1), acc);
+    if (c_lo < w && q < qend) {
+        Incidence nxt = incs[q];
+        for (; q < qend; ++q) {
+            const Incidence in = nxt;
+            if (q + 1 < qend) nxt = incs[q + 1];
+            if (in.cmax < c_lo || in.cmin >= c_hi) continue;
+            const int nI = in.nI, nJ = in.nJ;
+            const uint8_t *mp = imap + in.mapoff;
+            const int lcl = lane < nJ ? (int)mp[nI + lane] : 255;
+            const int jlo = __popcll(__ballot(lcl < c_lo));
+            const int jhi = __popcll(__ballot(lcl < c_hi));
+            if (jlo >= jhi) continue;
+            const int jb = jlo + (lane & 15);
+            const bool vb = jb < jhi;
+            const int colC = __shfl(lcl, vb ? jb : 0);
+            const int nrb = (nI + 15) >> 4;
+            const T *LK = Lx + in.valoff;
+            const int64_t ld = in.ld;
+            const int wk = in.wk;
+            typename Mfma<T>::acc_t acc[4] = {};
+            for (int k0 = 0; k0 < wk; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const bool vk = k < wk;
+                const int64_t ko = (int64_t)k * ld;
+                const T b = (vb && vk) ? LK[in.a0 + jb + ko] : T(0);
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+                for (int m = 0; m < 4; ++m) {
+                    if (m < nrb) {
+                        const int ar = 16 * m + (lane & 15);
+                        const T a = (ar < nI && vk) ? LK[in.b0 + ar + ko] : T(0);
+                        acc[m] = Mfma<T>::mma(a, b, acc[m]);
+                    }
+                }
+            }
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+            for (int m = 0; m < 4; ++m) {
+                if (m < nrb) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
-                        const int col = 32 * wc + 16 * n + (lane & 15);
-                        if (row < nI && col < nJ) {
-                            const int R = s_lr[row], Cc = s_lc[col];
-                            if (r0 + R >= Cc) C[Cc * LDC + R] -= acc[m][n][v];
+                        const int row = 16 * m + Mfma<T>::row(lane, v);
+                        if (vb && row < nI) {
+                            const int R = mp[row];
+                            if (R < nr && colC < w && r0 + R >= colC) C[colC * LDC + R] -= acc[m][v];
                         }
                     }
+                }
+            }
         }
-        __syncthreads();
     }
+    __syncthreads();
 
     if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
 
@@ -345,6 +450,10 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
     }
 }
 
+// Row tile t >= 1 of block J solves X := X L_JJ^{-T} against J's factored
+// diagonal block, blocked by 16 columns: one wavefront substitutes a
+// 16-column slice (rows in lanes), then all four wavefronts subtract its
+// product with the diagonal block's rows from the later columns.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
                                              const BlockDesc *__restrict__ blk,
@@ -368,17 +477,15 @@ __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
         X[c * LDC + i] = LJ[(int64_t)c * J.ld + r0 + i];
     }
     __syncthreads();
-    for (int k = 0; k < w; ++k) {
-        const T dkk = D[k * LDC + k];
-        for (int i = tid; i < nr; i += NT) X[k * LDC + i] /= dkk;
+    for (int c0 = 0; c0 < w; c0 += 16) {
+        const int wb = min(16, w - c0);
+        if ((tid >> 6) == 0) wave_subsolve(X, D, c0, wb, nr);
         __syncthreads();
-        const int nc = w - k - 1;
-        for (int idx = tid; idx < nc * nr; idx += NT) {
-            const int c = k + 1 + idx / nr;
-            const int i = idx % nr;
-            X[c * LDC + i] -= X[k * LDC + i] * D[k * LDC + c];
+        if (c0 + wb < w) {
+            // X[:, c0+wb:w] -= X[:, c0:c0+wb] * D[c0+wb:w, c0:c0+wb]^T (all rows)
+            block_update(X, X, D, 0, nr, c0 + wb, w, c0, wb, 64);
+            __syncthreads();
         }
-        __syncthreads();
     }
     for (int idx = tid; idx < nr * w; idx += NT) {
         const int i = idx % nr, c = idx / nr;
@@ -431,7 +538,7 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
         const unsigned g = (unsigned)(ph.t1 - ph.t0);
         Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
         if (ph.kind == kPhaseExternal)
-            k_external<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.incs, D.blk, D.rows, Lx,
+            k_external<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.incs, D.imap, D.blk, Lx,
                                            D.info);
         else if (ph.kind == kPhaseInternal)
             k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info);

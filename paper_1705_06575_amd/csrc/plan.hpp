@@ -42,15 +42,25 @@ struct Task {           // 16 bytes: one row tile of one block
     int32_t flags;      // kFuseFactor: the task also factors the block
 };
 
-// One descendant's contribution to one row tile of a target block J: K's
-// local rows [a0, a1) lie in J's columns, K's local rows [b0, b1) lie in
-// the tile's rows.
-struct Incidence {      // 24 bytes
-    int32_t K;
-    int32_t a0, a1;
-    int32_t b0, b1;
-    int32_t pad;
+// One descendant block K's contribution to one row tile of a target block
+// J: K's local rows [a0, a0 + nJ) lie in J's columns and K's local rows
+// [b0, b0 + nI) in the tile's rows.  map[mapoff ...] holds the nI
+// tile-relative rows of the latter, then the nJ tile columns of the former
+// (both increasing); cmin and cmax are the first and last of those columns.
+struct Incidence {      // 40 bytes, device-visible
+    int64_t valoff;     // K's panel offset
+    int64_t mapoff;     // offset into the relative-index map
+    int32_t ld;         // K's leading dimension
+    int32_t b0;
+    int32_t a0;
+    int16_t wk;         // K's width
+    uint8_t nI, nJ;
+    uint8_t cmin, cmax;
+    uint8_t pad[6];
 };
+
+static_assert(sizeof(Incidence) == 40, "Incidence layout is shared with the device");
+static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
 constexpr int32_t kFuseFactor = 1;
 
@@ -84,7 +94,15 @@ struct Plan {
     std::vector<int32_t> sparent;   // ns
     std::vector<int64_t> srowptr;   // ns+1
     std::vector<int32_t> srows;     // sum r_s
-    std::vector<int64_t> svaloff;   // ns+1, panel offsets
+
+    // ---- device supernodes: the fundamental ones after relaxed
+    // amalgamation (explicit zeros); panels and blocks are built on these
+    int32_t nds = 0;
+    std::vector<int32_t> dsptr;     // nds+1
+    std::vector<int32_t> dsparent;  // nds
+    std::vector<int64_t> dsrowptr;  // nds+1
+    std::vector<int32_t> dsrows;    // row lists (columns first, then the rows below)
+    std::vector<int64_t> dsvaloff;  // nds+1, panel offsets
     int64_t panel_entries = 0;
 
     // ---- device blocks
@@ -106,13 +124,14 @@ struct Plan {
     std::vector<int32_t> tJ;        // target block of each pair, grouped by K
 
     // supernodal schedule of the factorization
-    std::vector<int32_t> sbptr;     // ns+1: first block of each supernode
-    std::vector<int32_t> slevel;    // ns
+    std::vector<int32_t> sbptr;     // nds+1: first block of each device supernode
+    std::vector<int32_t> slevel;    // nds
     int32_t nslevels = 0;
     std::vector<Task> ftasks;       // all factor tasks in launch order
     std::vector<Phase> phases;      // launches
     std::vector<int64_t> iptr;      // ftasks.size()+1: incidences of external-update tasks
     std::vector<Incidence> incs;
+    std::vector<uint8_t> imap;      // tile-relative rows and columns of every incidence
     // arithmetic of each launch kind by the method's count (lower-triangle
     // products, one flop per multiply, add, divide and square root):
     // [0] scatter (none), [1] external, [2] trsm, [3] internal; the four sum
@@ -125,7 +144,7 @@ struct Plan {
 
 // Analysis entry point (symbolic.cpp).  Returns SYM_OK or a SYM_E* code.
 int analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, int ordering,
-            const int32_t *user_perm, int block_width, int nd_leaf, Plan &P);
+            const int32_t *user_perm, int block_width, int nd_leaf, bool relax, Plan &P);
 
 // Graph nested dissection on the symmetric pattern (ordering.cpp).
 // adj: CSR adjacency without self loops.  Returns perm[new] = old.

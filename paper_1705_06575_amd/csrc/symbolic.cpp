@@ -5,6 +5,7 @@
 // phase) and the map from A's entries into L's panels.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cstring>
 #include <numeric>
 
@@ -62,7 +63,7 @@ void permute_lower(int32_t n, const int64_t *Ap, const int32_t *Ai,
 }  // namespace
 
 int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
-            const int32_t *user_perm, int block_width, int nd_leaf, Plan &P)
+            const int32_t *user_perm, int block_width, int nd_leaf, bool relax, Plan &P)
 {
     auto t_start = std::chrono::steady_clock::now();
     if (n64 < 0 || n64 > INT32_MAX - 1) return SYM_EINVAL;
@@ -240,30 +241,91 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
             for (int32_t i : buf) P.srows[o++] = i;
         }
     }
-    P.svaloff.assign((size_t)ns + 1, 0);
-    for (int32_t s = 0; s < ns; ++s) {
-        int64_t w = P.sptr[s + 1] - P.sptr[s];
-        int64_t r = P.srowptr[s + 1] - P.srowptr[s];
-        P.svaloff[s + 1] = P.svaloff[s] + w * r;
+    // ------------------------------------------- relaxed device supernodes
+    // Adjacent child supernodes are merged into their parent when the
+    // explicit zeros this adds stay within the limits below (widths 4 / 16 /
+    // 48 with zero fractions 0.8 / 0.1 / 0.05 of the stored lower
+    // trapezoid).  The merged panel's row list is its columns followed by
+    // the parent's rows below them; every child row is in it (Eq. (1): a
+    // child's pattern below its columns lies in its parent's column pattern).
+    // The fundamental supernodes above stay the reported partition; only the
+    // device blocking uses the relaxed ones.  Stored zeros remain exactly
+    // zero through the factorization and the solves.
+    {
+        std::vector<int32_t> top;      // fundamental supernode on top of each relaxed one
+        std::vector<int32_t> first;    // first column
+        std::vector<double> ztrue;     // true entries of its columns
+        std::vector<int32_t> fund2r((size_t)ns, -1);
+        for (int32_t s = 0; s < ns; ++s) {
+            const int32_t f = P.sptr[s], wS = P.sptr[s + 1] - f;
+            const double rS = (double)(P.srowptr[s + 1] - P.srowptr[s]);
+            double zS = 0;
+            for (int32_t j = f; j < f + wS; ++j) zS += (double)P.colcount[j];
+            bool merged = false;
+            if (relax && !top.empty() && P.sparent[top.back()] == s && P.sptr[top.back() + 1] == f) {
+                const double Wn = (double)(f + wS - first.back());
+                const double E = rS - wS;                      // rows below the merged columns
+                const double stored = Wn * (Wn + 1) / 2 + Wn * E;
+                const double zeros = stored - (ztrue.back() + zS);
+                const double frac = stored > 0 ? zeros / stored : 0.0;
+                if (Wn <= 4 || (Wn <= 16 && frac < 0.8) || (Wn <= 48 && frac < 0.1) || frac < 0.05) {
+                    top.back() = s;
+                    ztrue.back() += zS;
+                    merged = true;
+                }
+            }
+            if (!merged) {
+                top.push_back(s);
+                first.push_back(f);
+                ztrue.push_back(zS);
+            }
+            fund2r[s] = (int32_t)top.size() - 1;
+        }
+        P.nds = (int32_t)top.size();
+        P.dsptr.assign(first.begin(), first.end());
+        P.dsptr.push_back(n);
+        P.dsparent.assign((size_t)P.nds, -1);
+        P.dsrowptr.assign((size_t)P.nds + 1, 0);
+        for (int32_t r = 0; r < P.nds; ++r) {
+            const int32_t t = top[r];
+            if (P.sparent[t] >= 0) P.dsparent[r] = fund2r[P.sparent[t]];
+            const int32_t wt = P.sptr[t + 1] - P.sptr[t];
+            const int64_t below = (P.srowptr[t + 1] - P.srowptr[t]) - wt;
+            P.dsrowptr[r + 1] = P.dsrowptr[r] + (P.dsptr[r + 1] - P.dsptr[r]) + below;
+        }
+        P.dsrows.resize((size_t)P.dsrowptr[P.nds]);
+        for (int32_t r = 0; r < P.nds; ++r) {
+            const int32_t t = top[r];
+            int64_t o = P.dsrowptr[r];
+            for (int32_t j = P.dsptr[r]; j < P.dsptr[r + 1]; ++j) P.dsrows[o++] = j;
+            const int32_t wt = P.sptr[t + 1] - P.sptr[t];
+            for (int64_t p = P.srowptr[t] + wt; p < P.srowptr[t + 1]; ++p) P.dsrows[o++] = P.srows[p];
+        }
     }
-    P.panel_entries = P.svaloff[ns];
+    P.dsvaloff.assign((size_t)P.nds + 1, 0);
+    for (int32_t s = 0; s < P.nds; ++s) {
+        int64_t w = P.dsptr[s + 1] - P.dsptr[s];
+        int64_t r = P.dsrowptr[s + 1] - P.dsrowptr[s];
+        P.dsvaloff[s + 1] = P.dsvaloff[s] + w * r;
+    }
+    P.panel_entries = P.dsvaloff[P.nds];
 
     // ------------------------------------------------------- device blocks
     const int32_t B = P.B;
     P.blk.clear();
     P.bptr.clear();
     P.col2blk.resize((size_t)n);
-    for (int32_t s = 0; s < ns; ++s) {
-        int32_t f = P.sptr[s], w = P.sptr[s + 1] - f;
-        int32_t r = (int32_t)(P.srowptr[s + 1] - P.srowptr[s]);
+    for (int32_t s = 0; s < P.nds; ++s) {
+        int32_t f = P.dsptr[s], w = P.dsptr[s + 1] - f;
+        int32_t r = (int32_t)(P.dsrowptr[s + 1] - P.dsrowptr[s]);
         for (int32_t k = 0; k * B < w; ++k) {
             BlockDesc d;
             d.col0 = f + k * B;
             d.w = std::min(B, w - k * B);
             d.r = r - k * B;
             d.ld = r;
-            d.rowoff = P.srowptr[s] + (int64_t)k * B;
-            d.valoff = P.svaloff[s] + (int64_t)k * B * r + (int64_t)k * B;
+            d.rowoff = P.dsrowptr[s] + (int64_t)k * B;
+            d.valoff = P.dsvaloff[s] + (int64_t)k * B * r + (int64_t)k * B;
             int32_t id = (int32_t)P.blk.size();
             for (int32_t j = d.col0; j < d.col0 + d.w; ++j) P.col2blk[j] = id;
             P.blk.push_back(d);
@@ -276,7 +338,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     P.bparent.assign((size_t)nb, -1);
     for (int32_t b = 0; b < nb; ++b) {
         const BlockDesc &d = P.blk[b];
-        if (d.r > d.w) P.bparent[b] = P.col2blk[P.srows[d.rowoff + d.w]];
+        if (d.r > d.w) P.bparent[b] = P.col2blk[P.dsrows[d.rowoff + d.w]];
     }
     P.blevel.assign((size_t)nb, 0);
     for (int32_t b = 0; b < nb; ++b)
@@ -300,7 +362,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     P.tptr.assign((size_t)nb + 1, 0);
     for (int32_t K = 0; K < nb; ++K) {
         const BlockDesc &d = P.blk[K];
-        const int32_t *rows = P.srows.data() + d.rowoff;
+        const int32_t *rows = P.dsrows.data() + d.rowoff;
         int32_t p = d.w;
         while (p < d.r) {
             int32_t J = P.col2blk[rows[p]];
@@ -320,7 +382,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         int64_t tq = 0;
         for (int32_t K = 0; K < nb; ++K) {
             const BlockDesc &d = P.blk[K];
-            const int32_t *rows = P.srows.data() + d.rowoff;
+            const int32_t *rows = P.dsrows.data() + d.rowoff;
             int32_t p = d.w;
             while (p < d.r) {
                 int32_t J = P.col2blk[rows[p]];
@@ -346,30 +408,32 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     //   for k = 1, 2, ...: internal updates of blocks c >= k by the now final
     //             block k-1 of the same supernode (right-looking), tile 0 of
     //             block k fused with its factorization; then block k's trsm.
-    P.sbptr.assign((size_t)ns + 1, 0);
-    for (int32_t s2 = 0; s2 < ns; ++s2) {
-        int32_t w = P.sptr[s2 + 1] - P.sptr[s2];
+    P.sbptr.assign((size_t)P.nds + 1, 0);
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) {
+        int32_t w = P.dsptr[s2 + 1] - P.dsptr[s2];
         P.sbptr[s2 + 1] = P.sbptr[s2] + (w + B - 1) / B;
     }
-    P.slevel.assign((size_t)ns, 0);
-    for (int32_t s2 = 0; s2 < ns; ++s2)
-        if (P.sparent[s2] >= 0)
-            P.slevel[P.sparent[s2]] = std::max(P.slevel[P.sparent[s2]], P.slevel[s2] + 1);
+    P.slevel.assign((size_t)P.nds, 0);
+    for (int32_t s2 = 0; s2 < P.nds; ++s2)
+        if (P.dsparent[s2] >= 0)
+            P.slevel[P.dsparent[s2]] = std::max(P.slevel[P.dsparent[s2]], P.slevel[s2] + 1);
     P.nslevels = 0;
-    for (int32_t s2 = 0; s2 < ns; ++s2) P.nslevels = std::max(P.nslevels, P.slevel[s2] + 1);
-    std::vector<int32_t> sl_ptr((size_t)P.nslevels + 1, 0), sl_list((size_t)ns);
-    for (int32_t s2 = 0; s2 < ns; ++s2) sl_ptr[P.slevel[s2] + 1]++;
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) P.nslevels = std::max(P.nslevels, P.slevel[s2] + 1);
+    std::vector<int32_t> sl_ptr((size_t)P.nslevels + 1, 0), sl_list((size_t)P.nds);
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) sl_ptr[P.slevel[s2] + 1]++;
     for (int32_t l = 0; l < P.nslevels; ++l) sl_ptr[l + 1] += sl_ptr[l];
     {
         std::vector<int32_t> fill(sl_ptr.begin(), sl_ptr.end() - 1);
-        for (int32_t s2 = 0; s2 < ns; ++s2) sl_list[fill[P.slevel[s2]]++] = s2;
+        for (int32_t s2 = 0; s2 < P.nds; ++s2) sl_list[fill[P.slevel[s2]]++] = s2;
     }
     auto ntiles = [&](int32_t J) { return (P.blk[J].r + kTileRows - 1) / kTileRows; };
     P.ftasks.clear();
     P.phases.clear();
     P.incs.clear();
     P.iptr.assign(1, 0);
-    std::vector<std::vector<Incidence>> per_tile;
+    struct RawInc { int32_t K, a0, a1, b0, b1; };
+    std::vector<std::vector<RawInc>> per_tile;
+    P.imap.clear();
     auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags) {
         P.ftasks.push_back(Task{J, t, K, flags});
         P.iptr.push_back((int64_t)P.incs.size());
@@ -379,6 +443,34 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         P.phases.back().t1 = (int64_t)P.ftasks.size();
         if (P.phases.back().t1 == P.phases.back().t0) P.phases.pop_back();
     };
+    // record one incidence of tile t of block J, with its relative indices
+    auto emit_inc = [&](int32_t J, int32_t t, const RawInc &ri) {
+        const BlockDesc &dJ = P.blk[J];
+        const BlockDesc &dK = P.blk[ri.K];
+        const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
+        const int32_t *rK = P.dsrows.data() + dK.rowoff;
+        const int32_t r0 = t * kTileRows;
+        const int32_t nr = std::min(kTileRows, dJ.r - r0);
+        Incidence in{};
+        in.valoff = dK.valoff;
+        in.mapoff = (int64_t)P.imap.size();
+        in.ld = dK.ld;
+        in.wk = (int16_t)dK.w;
+        in.b0 = ri.b0;
+        in.a0 = ri.a0;
+        in.nI = (uint8_t)(ri.b1 - ri.b0);
+        in.nJ = (uint8_t)(ri.a1 - ri.a0);
+        // tile rows of K's rows [b0, b1): a merge along J's sorted rows
+        int32_t p = r0;
+        for (int32_t q = ri.b0; q < ri.b1; ++q) {
+            while (p < r0 + nr && rJ[p] < rK[q]) ++p;
+            P.imap.push_back((uint8_t)(p - r0));
+        }
+        for (int32_t q = ri.a0; q < ri.a1; ++q) P.imap.push_back((uint8_t)(rK[q] - dJ.col0));
+        in.cmin = (uint8_t)(rK[ri.a0] - dJ.col0);
+        in.cmax = (uint8_t)(rK[ri.a1 - 1] - dJ.col0);
+        P.incs.push_back(in);
+    };
     for (int32_t l = 0; l < P.nslevels; ++l) {
         int32_t maxnb = 0;
         open_phase(kPhaseExternal);
@@ -387,7 +479,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
             maxnb = std::max(maxnb, P.sbptr[s2 + 1] - P.sbptr[s2]);
             for (int32_t J = P.sbptr[s2]; J < P.sbptr[s2 + 1]; ++J) {
                 const BlockDesc &dJ = P.blk[J];
-                const int32_t *rJ = P.srows.data() + dJ.rowoff;
+                const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
                 const int32_t nt = ntiles(J);
                 if ((int32_t)per_tile.size() < nt) per_tile.resize((size_t)nt);
                 for (int32_t t = 0; t < nt; ++t) per_tile[t].clear();
@@ -395,14 +487,14 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                     const Pair &pr = P.pairs[p];
                     if (pr.K >= P.sbptr[s2]) break;     // internal pairs come last
                     const BlockDesc &dK = P.blk[pr.K];
-                    const int32_t *rK = P.srows.data() + dK.rowoff;
+                    const int32_t *rK = P.dsrows.data() + dK.rowoff;
                     int32_t pos = pr.a0;
                     while (pos < dK.r) {
                         const int32_t li = (int32_t)(std::lower_bound(rJ, rJ + dJ.r, rK[pos]) - rJ);
                         const int32_t t = li / kTileRows;
                         const int32_t last = rJ[std::min((t + 1) * kTileRows, dJ.r) - 1];
                         const int32_t end = (int32_t)(std::upper_bound(rK + pos, rK + dK.r, last) - rK);
-                        per_tile[t].push_back(Incidence{pr.K, pr.a0, pr.a1, pos, end, 0});
+                        per_tile[t].push_back(RawInc{pr.K, pr.a0, pr.a1, pos, end});
                         pos = end;
                     }
                 }
@@ -410,7 +502,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                 for (int32_t t = 0; t < nt; ++t) {
                     const bool fuse = first && t == 0;
                     if (per_tile[t].empty() && !fuse) continue;
-                    for (const Incidence &in : per_tile[t]) P.incs.push_back(in);
+                    for (const RawInc &ri : per_tile[t]) emit_inc(J, t, ri);
                     push_task(J, t, -1, fuse ? kFuseFactor : 0);
                 }
             }
@@ -445,47 +537,49 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     }
 
     // ----------------------------------- arithmetic per launch kind
+    // The method's count sum_k |L_k|^2 split by the launch kind that performs
+    // it, on the true pattern of L (stored zeros excluded).  Column k
+    // contributes a square root, |L_k| - 1 divisions and 2 flops for every
+    // pair j <= i of its rows below k; the pair (j, i) is done by an external
+    // update if j lies in another device supernode, by an internal update if
+    // j lies in another block of k's device supernode, and otherwise inside
+    // k's block: by the fused factorization of its tile 0 (kind external
+    // for a supernode's first block, internal otherwise) when row i is among
+    // the block's first 64 rows, else by an off-diagonal tile solve.
     {
-        auto lower_pairs = [](int64_t nrows, int64_t r0, int64_t ncols) -> double {
-            // pairs (i, j), i in [r0, r0 + nrows), j in [0, ncols), with j <= i
-            double s2 = 0;
-            for (int64_t i = r0; i < r0 + nrows; ++i) s2 += (double)std::min<int64_t>(i + 1, ncols);
-            return s2;
-        };
-        auto panel = [](int64_t nrows, int64_t r0, int64_t w) -> double {
-            // within-block work of rows [r0, r0 + nrows): sum_{j <= min(i, w-1)} (2j + 1)
-            double s2 = 0;
-            for (int64_t i = r0; i < r0 + nrows; ++i) {
-                int64_t m = std::min<int64_t>(i + 1, w);
-                s2 += (double)m * (double)m;
-            }
-            return s2;
-        };
         for (double &f : P.kind_flops) f = 0.0;
-        for (const Phase &ph : P.phases) {
-            for (int64_t q = ph.t0; q < ph.t1; ++q) {
-                const Task &tk = P.ftasks[q];
-                const BlockDesc &J = P.blk[tk.J];
-                const int64_t r0 = (int64_t)tk.t * kTileRows;
-                const int64_t nr = std::min<int64_t>(kTileRows, J.r - r0);
-                if (ph.kind == kPhaseExternal) {
-                    for (int64_t e = P.iptr[q]; e < P.iptr[q + 1]; ++e) {
-                        const Incidence &in = P.incs[e];
-                        const int64_t nI = in.b1 - in.b0, nJ = in.a1 - in.a0;
-                        double pairs = 0;
-                        if (tk.t == 0)
-                            for (int64_t i = 0; i < nI; ++i) pairs += (double)std::min<int64_t>(i + 1, nJ);
-                        else
-                            pairs = (double)nI * (double)nJ;
-                        P.kind_flops[1] += 2.0 * P.blk[in.K].w * pairs;
-                    }
-                    if (tk.flags & kFuseFactor) P.kind_flops[1] += panel(nr, r0, J.w);
-                } else if (ph.kind == kPhaseInternal) {
-                    P.kind_flops[3] += 2.0 * P.blk[tk.K].w * lower_pairs(nr, r0, J.w);
-                    if (tk.flags & kFuseFactor) P.kind_flops[3] += panel(nr, r0, J.w);
-                } else {
-                    P.kind_flops[2] += panel(nr, r0, J.w);
+        std::vector<int32_t> col2ds((size_t)n);
+        for (int32_t r = 0; r < P.nds; ++r)
+            for (int32_t j = P.dsptr[r]; j < P.dsptr[r + 1]; ++j) col2ds[j] = r;
+        std::vector<int32_t> blk_first((size_t)P.nb, 0);
+        for (int32_t r = 0; r < P.nds; ++r) blk_first[P.col2blk[P.dsptr[r]]] = 1;
+        for (int32_t s2 = 0; s2 < ns; ++s2) {
+            const int32_t *frows = P.srows.data() + P.srowptr[s2];
+            const int32_t fr = (int32_t)(P.srowptr[s2 + 1] - P.srowptr[s2]);
+            for (int32_t k = P.sptr[s2]; k < P.sptr[s2 + 1]; ++k) {
+                const int32_t *r = frows + (k - P.sptr[s2]);
+                const int64_t c = fr - (k - P.sptr[s2]);
+                const int32_t bk = P.col2blk[k];
+                const BlockDesc &d = P.blk[bk];
+                const int fused = blk_first[bk] ? 1 : 3;
+                const int32_t *drows = P.dsrows.data() + d.rowoff;
+                const int32_t thr = d.r > kTileRows ? drows[kTileRows - 1] : INT32_MAX;
+                const int64_t q1 = std::upper_bound(r, r + c, d.col0 + d.w - 1) - r;
+                const int64_t q2 = std::upper_bound(r, r + c, P.dsptr[col2ds[k] + 1] - 1) - r;
+                const int64_t t0 = std::upper_bound(r, r + c, thr) - r;
+                P.kind_flops[fused] += 1.0 + (double)(t0 - 1);
+                P.kind_flops[2] += (double)(c - t0);
+                for (int64_t p = 1; p < q1; ++p) {
+                    P.kind_flops[fused] += 2.0 * (double)std::max<int64_t>(0, t0 - p);
+                    P.kind_flops[2] += 2.0 * (double)(c - std::max<int64_t>(p, t0));
                 }
+                // sum_{p=a}^{b-1} (c - p)
+                auto tri = [c](int64_t a, int64_t b) -> double {
+                    if (b <= a) return 0.0;
+                    return (double)(b - a) * (double)c - ((double)(a + b - 1) * (double)(b - a)) / 2.0;
+                };
+                P.kind_flops[3] += 2.0 * tri(q1, q2);
+                P.kind_flops[1] += 2.0 * tri(q2, c);
             }
         }
     }
@@ -494,7 +588,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     P.amap.resize((size_t)P.nnzA);
     for (int32_t c = 0; c < n; ++c) {
         const BlockDesc &d = P.blk[P.col2blk[c]];
-        const int32_t *rows = P.srows.data() + d.rowoff;
+        const int32_t *rows = P.dsrows.data() + d.rowoff;
         int32_t lc = c - d.col0;
         for (int64_t p = C.cp[c]; p < C.cp[c + 1]; ++p) {
             int32_t row = C.ci[p];

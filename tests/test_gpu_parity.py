@@ -109,6 +109,23 @@ def test_small_random_matrices(S, orc, torch_cuda):
         _check_against_oracle(S, orc, torch_cuda, w)
 
 
+@pytest.mark.parametrize("amalgamate", [False, True])
+def test_amalgamation_modes(S, orc, torch_cuda, amalgamate):
+    """The factor and solves with and without explicit-zero amalgamation."""
+    torch = torch_cuda
+    for w in [W.config2(14), W.knn_instance(5, nv=900)]:
+        _say(f"case {w.name} amalgamate={amalgamate}")
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, amalgamate=amalgamate)
+        an.factor(torch.from_numpy(w.Ax).cuda())
+        assert an.status() == 0
+        f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+        Lx = an.export_factor()
+        eL = _rel(Lx, f["Lx"])
+        res = orc.llt_residual(w.n, f["Cp"], f["Ci"], f["Cx"], f["Lp"], f["Li"], Lx)
+        _say(f"  factor rel diff {eL:.3e} llt residual {res:.3e}")
+        assert res <= 1e-13 and eL <= 1e-10
+
+
 def test_dense_multi_block_multi_tile(S, orc, torch_cuda):
     """Fully dense 200 x 200: one supernode cut into 4 blocks of <= 64
     columns with up to 4 row tiles each (exercises the off-diagonal tile

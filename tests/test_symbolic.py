@@ -175,16 +175,34 @@ def test_empty_matrix(S):
 
 
 def test_block_structure(S, orc):
-    """Device blocks tile each supernode into pieces of at most B columns."""
+    """Device blocks tile each (fundamental, without amalgamation) supernode
+    into pieces of at most B columns."""
     for B in (16, 32, 64):
         w = W.random_spd(150, 0.9, np.random.default_rng(4))
-        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, block_width=B)
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, block_width=B, amalgamate=False)
         sp = an.get("super")
         bp = an.get("blocks")
         assert set(sp.tolist()) <= set(bp.tolist())
         assert (np.diff(bp) <= B).all() and bp[-1] == w.n
         lv = an.get("blevel")
         assert lv.max() + 1 == an.stat("nlevels")
+
+
+def test_amalgamation_keeps_reported_structure(S, orc):
+    """Relaxed amalgamation changes only the device panels: the reported
+    fundamental supernodes and L pattern are unchanged, every device
+    supernode boundary is a fundamental one, and the stored lower trapezoid
+    covers nnz(L) plus explicit zeros."""
+    for w in [W.config1(), W.config2(16), W.knn_instance(4, nv=1000)]:
+        a0 = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, amalgamate=False)
+        a1 = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, amalgamate=True)
+        for k in ("parent", "colcount", "Lp", "Li", "super"):
+            assert np.array_equal(a0.get(k), a1.get(k))
+        assert set(a1.get("blocks").tolist()) <= set(a0.get("blocks").tolist()) | set(range(w.n + 1))
+        assert a1.stat("ndsuper") <= a0.stat("ndsuper") == a0.stat("nsuper")
+        assert a0.stat("stored_lower") == a0.stat("nnzL")
+        assert a1.stat("stored_lower") >= a1.stat("nnzL")
+        assert a1.stat("flops") == a0.stat("flops")
 
 
 def test_kind_flops_partition_the_method_count(S):
