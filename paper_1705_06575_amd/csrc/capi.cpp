@@ -16,7 +16,8 @@ struct sym_plan {
     sym::Plan P;
     size_t ws_bytes = 0;
     size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_incs = 0, off_imap = 0,
-           off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_info = 0;
+           off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
+           off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
     bool factored = false;
@@ -32,11 +33,10 @@ struct sym_plan {
 struct sym_rhs_plan {
     sym_plan *h = nullptr;
     std::vector<int32_t> reach;      // permuted columns, increasing
-    std::vector<int32_t> blocks;     // touched blocks grouped by level
-    std::vector<int32_t> cstart;     // first reached local column per touched block
+    std::vector<sym::SolveTask> tasks;  // forward tasks of the touched blocks, grouped by level
     std::vector<int32_t> bpos;       // permuted positions of b's nonzeros
-    std::vector<int64_t> level_ptr;  // groups of `blocks` per nonempty level
-    size_t ws_bytes = 0, off_blocks = 0, off_cstart = 0, off_bpos = 0;
+    std::vector<int64_t> level_ptr;  // groups of `tasks` per nonempty level
+    size_t ws_bytes = 0, off_tasks = 0, off_bpos = 0;
     sym::DeviceRhs R;
     bool bound = false;
 };
@@ -63,6 +63,9 @@ void layout(sym_plan *h)
     h->off_amap = take(sizeof(int64_t) * P.amap.size());
     h->off_perm = take(sizeof(int32_t) * P.perm.size());
     h->off_vec = take(sizeof(double) * (size_t)P.n);
+    h->off_vec2 = take(sizeof(double) * (size_t)P.n);
+    h->off_ftk = take(sizeof(sym::SolveTask) * P.fwd_tasks.size());
+    h->off_btk = take(sizeof(sym::SolveTask) * P.bwd_tasks.size());
     h->off_info = take(sizeof(int32_t) * 4);
     h->ws_bytes = o;
 }
@@ -143,6 +146,9 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.amap = (int64_t *)(base + h->off_amap);
     D.perm = (int32_t *)(base + h->off_perm);
     D.vec = (double *)(base + h->off_vec);
+    D.vec2 = (double *)(base + h->off_vec2);
+    D.fwd_tasks = (sym::SolveTask *)(base + h->off_ftk);
+    D.bwd_tasks = (sym::SolveTask *)(base + h->off_btk);
     D.info = (int32_t *)(base + h->off_info);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
@@ -154,6 +160,10 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.level_blocks, P.level_blocks.data(), sizeof(int32_t) * P.level_blocks.size(), s);
     if (e == hipSuccess) e = upload(D.amap, P.amap.data(), sizeof(int64_t) * P.amap.size(), s);
     if (e == hipSuccess) e = upload(D.perm, P.perm.data(), sizeof(int32_t) * P.perm.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.fwd_tasks, P.fwd_tasks.data(), sizeof(sym::SolveTask) * P.fwd_tasks.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.bwd_tasks, P.bwd_tasks.data(), sizeof(sym::SolveTask) * P.bwd_tasks.size(), s);
     if (e != hipSuccess) return SYM_EHIP;
     h->bound = true;
     h->factored = false;
@@ -180,8 +190,8 @@ int sym_solve_lower(sym_handle h, const double *b_dev, double *y_dev, void *stre
     hipStream_t s = (hipStream_t)stream;
     h->stream = s;
     if (b_dev == y_dev) return SYM_EINVAL;
-    if (sym::launch_perm_gather(h->P, h->D, b_dev, y_dev, s) != hipSuccess) return SYM_EHIP;
-    if (sym::launch_fwd(h->P, h->D, y_dev, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_perm_gather(h->P, h->D, b_dev, h->D.vec, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_fwd(h->P, h->D, h->D.vec, y_dev, s) != hipSuccess) return SYM_EHIP;
     return SYM_OK;
 }
 
@@ -201,9 +211,9 @@ int sym_solve(sym_handle h, double *bx_dev, void *stream)
     if (!h->bound || !h->factored) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     h->stream = s;
-    double *y = h->D.vec;
-    if (sym::launch_perm_gather(h->P, h->D, bx_dev, y, s) != hipSuccess) return SYM_EHIP;
-    if (sym::launch_fwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
+    double *acc = h->D.vec, *y = h->D.vec2;
+    if (sym::launch_perm_gather(h->P, h->D, bx_dev, acc, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_fwd(h->P, h->D, acc, y, s) != hipSuccess) return SYM_EHIP;
     if (sym::launch_bwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
     if (sym::launch_perm_scatter(h->P, h->D, y, bx_dev, s) != hipSuccess) return SYM_EHIP;
     return SYM_OK;
@@ -242,16 +252,16 @@ int sym_rhs_analyze(sym_handle h, int64_t nb, const int32_t *bi, sym_rhs *out)
         r->level_ptr.push_back(0);
         int32_t cur = -1;
         for (int32_t b : touched) {
-            if (P.blevel[b] != cur && !r->blocks.empty()) r->level_ptr.push_back((int64_t)r->blocks.size());
+            if (P.blevel[b] != cur && !r->tasks.empty()) r->level_ptr.push_back((int64_t)r->tasks.size());
             cur = P.blevel[b];
-            r->blocks.push_back(b);
-            r->cstart.push_back(bfirst[b]);
+            const int32_t nch =
+                std::max(1, (P.blk[b].r - P.blk[b].w + sym::kSolveChunk - 1) / sym::kSolveChunk);
+            for (int32_t ch = 0; ch < nch; ++ch) r->tasks.push_back(sym::SolveTask{b, ch, bfirst[b], 0});
         }
-        if (!r->blocks.empty()) r->level_ptr.push_back((int64_t)r->blocks.size());
+        if (!r->tasks.empty()) r->level_ptr.push_back((int64_t)r->tasks.size());
         size_t o = 0;
         auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
-        r->off_blocks = take(sizeof(int32_t) * r->blocks.size());
-        r->off_cstart = take(sizeof(int32_t) * r->cstart.size());
+        r->off_tasks = take(sizeof(sym::SolveTask) * r->tasks.size());
         r->off_bpos = take(sizeof(int32_t) * r->bpos.size());
         r->ws_bytes = std::max<size_t>(o, 256);
     } catch (const std::bad_alloc &) {
@@ -275,11 +285,9 @@ int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream)
     if (bytes < r->ws_bytes || ((uintptr_t)dev_ws & 255)) return SYM_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)dev_ws;
-    r->R.blocks = (int32_t *)(base + r->off_blocks);
-    r->R.cstart = (int32_t *)(base + r->off_cstart);
+    r->R.tasks = (sym::SolveTask *)(base + r->off_tasks);
     r->R.bpos = (int32_t *)(base + r->off_bpos);
-    hipError_t e = upload(r->R.blocks, r->blocks.data(), sizeof(int32_t) * r->blocks.size(), s);
-    if (e == hipSuccess) e = upload(r->R.cstart, r->cstart.data(), sizeof(int32_t) * r->cstart.size(), s);
+    hipError_t e = upload(r->R.tasks, r->tasks.data(), sizeof(sym::SolveTask) * r->tasks.size(), s);
     if (e == hipSuccess) e = upload(r->R.bpos, r->bpos.data(), sizeof(int32_t) * r->bpos.size(), s);
     if (e != hipSuccess) return SYM_EHIP;
     r->bound = true;
@@ -295,7 +303,7 @@ int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double
     hipStream_t s = (hipStream_t)stream;
     h->stream = s;
     if (sym::launch_fwd_sparse(h->P, h->D, r->R, r->level_ptr, (int64_t)r->bpos.size(), bv_dev,
-                               y_dev, s) != hipSuccess)
+                               h->D.vec, y_dev, s) != hipSuccess)
         return SYM_EHIP;
     return SYM_OK;
 }

@@ -22,14 +22,16 @@ struct DevicePlan {
     int32_t *level_blocks = nullptr;// nb, grouped by level
     int64_t *amap = nullptr;        // nnzA
     int32_t *perm = nullptr;        // n
-    double *vec = nullptr;          // n scratch
+    double *vec = nullptr;          // n scratch (forward accumulator)
+    double *vec2 = nullptr;         // n scratch (forward output in full solves)
+    SolveTask *fwd_tasks = nullptr; // forward-sweep tasks grouped by level
+    SolveTask *bwd_tasks = nullptr; // backward off-diagonal chunk tasks grouped by level
     int32_t *info = nullptr;        // [0] = smallest failing column (permuted), INT32_MAX if none
 };
 
 // Reach-pruned forward sweep schedule, device view.
 struct DeviceRhs {
-    int32_t *blocks = nullptr;      // touched blocks grouped by level
-    int32_t *cstart = nullptr;      // first reached local column of each touched block
+    SolveTask *tasks = nullptr;     // forward tasks of the touched blocks, grouped by level
     int32_t *bpos = nullptr;        // nb_rhs: permuted positions of b's nonzeros
 };
 
@@ -51,10 +53,10 @@ hipError_t launch_perm_gather(const Plan &P, const DevicePlan &D, const double *
                               hipStream_t s);
 hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double *y, double *x,
                                hipStream_t s);
-hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s);
+hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *acc, double *out, hipStream_t s);
 hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s);
 hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs &R,
                              const std::vector<int64_t> &level_ptr, int64_t nbeta,
-                             const double *bv, double *y, hipStream_t s);
+                             const double *bv, double *acc, double *out, hipStream_t s);
 
 }  // namespace sym

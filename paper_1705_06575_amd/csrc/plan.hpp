@@ -72,6 +72,14 @@ struct Phase {
 };
 
 constexpr int kTileRows = 64;   // T: rows per factor task tile
+constexpr int kSolveChunk = 256; // rows below the diagonal per forward-solve task
+
+struct SolveTask {      // 16 bytes: one chunk of one block in a forward sweep
+    int32_t J;
+    int32_t chunk;      // rows [w + chunk*kSolveChunk, ...) below the diagonal
+    int32_t c0;         // first column of the block to solve (reach-pruned sweeps)
+    int32_t pad;
+};
 
 struct Plan {
     // ---- input
@@ -115,6 +123,10 @@ struct Plan {
     int32_t nlevels = 0;
     std::vector<int32_t> level_ptr;     // nlevels+1 into level_blocks
     std::vector<int32_t> level_blocks;  // nb, blocks sorted by level (stable in id)
+    std::vector<int64_t> fwd_level_ptr; // nlevels+1 into fwd_tasks
+    std::vector<SolveTask> fwd_tasks;   // forward-sweep tasks grouped by level
+    std::vector<int64_t> bwd_level_ptr; // nlevels+1 into bwd_tasks
+    std::vector<SolveTask> bwd_tasks;   // backward off-diagonal chunks (blocks with rows below)
 
     // descendant pairs, grouped by target block
     std::vector<int64_t> dptr;      // nb+1

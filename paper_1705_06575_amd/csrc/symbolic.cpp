@@ -355,6 +355,28 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         for (int32_t b = 0; b < nb; ++b) P.level_blocks[fill[P.blevel[b]]++] = b;
     }
 
+    // forward-sweep tasks: every block of a level, in chunks of its rows
+    P.fwd_level_ptr.assign((size_t)P.nlevels + 1, 0);
+    P.fwd_tasks.clear();
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+            const int32_t b = P.level_blocks[q];
+            const int32_t nch = std::max(1, (P.blk[b].r - P.blk[b].w + kSolveChunk - 1) / kSolveChunk);
+            for (int32_t c = 0; c < nch; ++c) P.fwd_tasks.push_back(SolveTask{b, c, 0, 0});
+        }
+        P.fwd_level_ptr[l + 1] = (int64_t)P.fwd_tasks.size();
+    }
+    P.bwd_level_ptr.assign((size_t)P.nlevels + 1, 0);
+    P.bwd_tasks.clear();
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+            const int32_t b = P.level_blocks[q];
+            const int32_t nch = (P.blk[b].r - P.blk[b].w + kSolveChunk - 1) / kSolveChunk;
+            for (int32_t c = 0; c < nch; ++c) P.bwd_tasks.push_back(SolveTask{b, c, 0, 0});
+        }
+        P.bwd_level_ptr[l + 1] = (int64_t)P.bwd_tasks.size();
+    }
+
     // ------------------------------------------ descendant pairs (prune set)
     // Block K's rows below its own columns fall into runs of consecutive
     // local rows that lie in one target block's columns.
