@@ -326,6 +326,8 @@ __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
             if (in.cmax < c_lo || in.cmin >= c_hi) continue;
             const int nI = in.nI, nJ = in.nJ;
             const uint8_t *mp = imap + in.mapoff;
+            // relative indices: lane l holds tile row l and tile column l
+            const int lrl = lane < nI ? (int)mp[lane] : 0;
             const int lcl = lane < nJ ? (int)mp[nI + lane] : 255;
             const int jlo = __popcll(__ballot(lcl < c_lo));
             const int jhi = __popcll(__ballot(lcl < c_hi));
@@ -338,19 +340,37 @@ __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
             const int64_t ld = in.ld;
             const int wk = in.wk;
             typename Mfma<T>::acc_t acc[4] = {};
-            for (int k0 = 0; k0 < wk; k0 += 4) {
-                const int k = k0 + (lane >> 4);
+            // one k-step of operands is fetched ahead of the products
+            T b_nx, a_nx[4];
+            {
+                const int k = lane >> 4;
                 const bool vk = k < wk;
-                const int64_t ko = (int64_t)k * ld;
-                const T b = (vb && vk) ? LK[in.a0 + jb + ko] : T(0);
+                b_nx = (vb && vk) ? LK[in.a0 + jb + (int64_t)k * ld] : T(0);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    if (m < nrb) {
+                    const int ar = 16 * m + (lane & 15);
+                    a_nx[m] = (ar < nI && vk) ? LK[in.b0 + ar + (int64_t)k * ld] : T(0);
+                }
+            }
+            for (int k0 = 0; k0 < wk; k0 += 4) {
+                const T b = b_nx;
+                T a[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) a[m] = a_nx[m];
+                {
+                    const int k = k0 + 4 + (lane >> 4);
+                    const bool vk = k < wk;
+                    const int64_t ko = (int64_t)k * ld;
+                    b_nx = (vb && vk) ? LK[in.a0 + jb + ko] : T(0);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
                         const int ar = 16 * m + (lane & 15);
-                        const T a = (ar < nI && vk) ? LK[in.b0 + ar + ko] : T(0);
-                        acc[m] = Mfma<T>::mma(a, b, acc[m]);
+                        a_nx[m] = (m < nrb && ar < nI && vk) ? LK[in.b0 + ar + ko] : T(0);
                     }
                 }
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (m < nrb) acc[m] = Mfma<T>::mma(a[m], b, acc[m]);
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -358,10 +378,9 @@ __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int row = 16 * m + Mfma<T>::row(lane, v);
-                        if (vb && row < nI) {
-                            const int R = mp[row];
-                            if (R < nr && colC < w && r0 + R >= colC) C[colC * LDC + R] -= acc[m][v];
-                        }
+                        const int R = __shfl(lrl, row);
+                        if (vb && row < nI && R < nr && colC < w && r0 + R >= colC)
+                            C[colC * LDC + R] -= acc[m][v];
                     }
                 }
             }
