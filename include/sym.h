@@ -130,6 +130,21 @@ int sym_solve_lower(sym_handle h, const double *b_dev, double *y_dev, void *stre
 int sym_solve_upper(sym_handle h, double *y_dev, void *stream);
 
 /*
+ * Solve A x = b with the current factor (FP64, or FP32 for mixed precision)
+ * and FP64 iterative refinement on the device: x0 = P^T L^-T L^-1 P b, then
+ * repeatedly r = b - A x in FP64 (Ax_dev: the values the factor was computed
+ * from, in sym_analyze's order), eta = ||r||_inf / (||A||_inf ||x||_inf +
+ * ||b||_inf) (normwise backward error), stopping when eta <= tol or after
+ * maxit corrections, else x += solve(r).  b_dev, x_dev: device double[n],
+ * original ordering, distinct.  Synchronizes the stream once per iteration
+ * to read eta.  *iters (may be NULL): corrections applied; *eta (may be
+ * NULL): final backward error (NaN if the factor failed).  Errors:
+ * SYM_EINVAL, SYM_ESTATE (no factor), SYM_EHIP.
+ */
+int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *x_dev, double tol,
+               int32_t maxit, void *stream, int32_t *iters, double *eta);
+
+/*
  * Reach-set inspector for one right-hand-side pattern, host only (Section
  * 1.1, Gilbert-Peierls: Reach_L(beta) is the set of columns reachable in the
  * dependence graph of L from beta = {i : b_i != 0}; numerical cancellation

@@ -17,6 +17,7 @@ struct sym_plan {
     size_t ws_bytes = 0;
     size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_incs = 0, off_imap = 0,
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
+           off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -67,6 +68,11 @@ void layout(sym_plan *h)
     h->off_ftk = take(sizeof(sym::SolveTask) * P.fwd_tasks.size());
     h->off_btk = take(sizeof(sym::SolveTask) * P.bwd_tasks.size());
     h->off_info = take(sizeof(int32_t) * 4);
+    h->off_vec3 = take(sizeof(double) * (size_t)P.n);
+    h->off_arp = take(sizeof(int64_t) * P.arowptr.size());
+    h->off_acol = take(sizeof(int32_t) * P.acol.size());
+    h->off_aval = take(sizeof(int64_t) * P.aval.size());
+    h->off_red = take(sizeof(double) * 4);
     h->ws_bytes = o;
 }
 
@@ -150,6 +156,11 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.fwd_tasks = (sym::SolveTask *)(base + h->off_ftk);
     D.bwd_tasks = (sym::SolveTask *)(base + h->off_btk);
     D.info = (int32_t *)(base + h->off_info);
+    D.vec3 = (double *)(base + h->off_vec3);
+    D.arowptr = (int64_t *)(base + h->off_arp);
+    D.acol = (int32_t *)(base + h->off_acol);
+    D.aval = (int64_t *)(base + h->off_aval);
+    D.red = (double *)(base + h->off_red);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
@@ -164,6 +175,9 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
         e = upload(D.fwd_tasks, P.fwd_tasks.data(), sizeof(sym::SolveTask) * P.fwd_tasks.size(), s);
     if (e == hipSuccess)
         e = upload(D.bwd_tasks, P.bwd_tasks.data(), sizeof(sym::SolveTask) * P.bwd_tasks.size(), s);
+    if (e == hipSuccess) e = upload(D.arowptr, P.arowptr.data(), sizeof(int64_t) * P.arowptr.size(), s);
+    if (e == hipSuccess) e = upload(D.acol, P.acol.data(), sizeof(int32_t) * P.acol.size(), s);
+    if (e == hipSuccess) e = upload(D.aval, P.aval.data(), sizeof(int64_t) * P.aval.size(), s);
     if (e != hipSuccess) return SYM_EHIP;
     h->bound = true;
     h->factored = false;
@@ -216,6 +230,47 @@ int sym_solve(sym_handle h, double *bx_dev, void *stream)
     if (sym::launch_fwd(h->P, h->D, acc, y, s) != hipSuccess) return SYM_EHIP;
     if (sym::launch_bwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
     if (sym::launch_perm_scatter(h->P, h->D, y, bx_dev, s) != hipSuccess) return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *x_dev, double tol,
+               int32_t maxit, void *stream, int32_t *iters, double *eta)
+{
+    if (!h || ((!Ax_dev || !b_dev || !x_dev) && h->P.n) || maxit < 0 || !(tol >= 0.0)) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    const sym::Plan &P = h->P;
+    const sym::DevicePlan &D = h->D;
+    const size_t bytes = sizeof(double) * (size_t)P.n;
+    if (P.n == 0) {
+        if (iters) *iters = 0;
+        if (eta) *eta = 0.0;
+        return SYM_OK;
+    }
+    // x0 = solve(b)
+    if (hipMemcpyAsync(x_dev, b_dev, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SYM_EHIP;
+    int rc = sym_solve(h, x_dev, stream);
+    if (rc != SYM_OK) return rc;
+    double red[4] = {0, 0, 0, 0};
+    double e = 0.0;
+    int32_t it = 0;
+    for (;;) {
+        if (sym::launch_residual(P, D, Ax_dev, b_dev, x_dev, D.vec3, it == 0, s) != hipSuccess) return SYM_EHIP;
+        double cur[4];
+        if (hipMemcpyAsync(cur, D.red, sizeof(cur), hipMemcpyDeviceToHost, s) != hipSuccess) return SYM_EHIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return SYM_EHIP;
+        if (it == 0) red[1] = cur[1];
+        const double den = red[1] * cur[2] + cur[3];
+        e = den > 0.0 ? cur[0] / den : cur[0];
+        if (!(e > tol) || it >= maxit) break;      // also stops on NaN
+        rc = sym_solve(h, D.vec3, stream);           // correction, in place
+        if (rc != SYM_OK) return rc;
+        if (sym::launch_axpy(P, x_dev, D.vec3, s) != hipSuccess) return SYM_EHIP;
+        ++it;
+    }
+    if (iters) *iters = it;
+    if (eta) *eta = e;
     return SYM_OK;
 }
 

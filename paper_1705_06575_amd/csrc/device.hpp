@@ -27,6 +27,11 @@ struct DevicePlan {
     SolveTask *fwd_tasks = nullptr; // forward-sweep tasks grouped by level
     SolveTask *bwd_tasks = nullptr; // backward off-diagonal chunk tasks grouped by level
     int32_t *info = nullptr;        // [0] = smallest failing column (permuted), INT32_MAX if none
+    double *vec3 = nullptr;         // n scratch (refinement residual / correction)
+    int64_t *arowptr = nullptr;     // full symmetric rows of A (original ordering)
+    int32_t *acol = nullptr;
+    int64_t *aval = nullptr;
+    double *red = nullptr;          // reduction scalars of refinement
 };
 
 // Reach-pruned forward sweep schedule, device view.
@@ -58,5 +63,13 @@ hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t
 hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs &R,
                              const std::vector<int64_t> &level_ptr, int64_t nbeta,
                              const double *bv, double *acc, double *out, hipStream_t s);
+
+// ---- iterative refinement (refine.hip)
+// r = b - A x (FP64); red[0] = max |r_i|, red[1] = max_i sum_j |A_ij|,
+// red[2] = max |x_i|, red[3] = max |b_i| (the norms of eta_inf).
+hipError_t launch_residual(const Plan &P, const DevicePlan &D, const double *Ax, const double *b,
+                           const double *x, double *r, bool with_anorm, hipStream_t s);
+// x += d
+hipError_t launch_axpy(const Plan &P, double *x, const double *d, hipStream_t s);
 
 }  // namespace sym

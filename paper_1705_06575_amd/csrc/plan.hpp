@@ -152,6 +152,13 @@ struct Plan {
 
     // A -> L map (offset into L's values for every entry of A, input order)
     std::vector<int64_t> amap;
+
+    // full symmetric pattern of A in the original ordering, by rows, for the
+    // FP64 residual of iterative refinement: row i holds the entries
+    // (i, acol[p]) whose value is Ax[aval[p]] (the stored lower entry)
+    std::vector<int64_t> arowptr;   // n+1
+    std::vector<int32_t> acol;
+    std::vector<int64_t> aval;
 };
 
 // Analysis entry point (symbolic.cpp).  Returns SYM_OK or a SYM_E* code.

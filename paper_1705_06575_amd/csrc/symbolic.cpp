@@ -621,6 +621,30 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         }
     }
 
+    // ------------------------------------ full symmetric rows of A (residual)
+    P.arowptr.assign((size_t)n + 1, 0);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p) {
+            P.arowptr[Ai[p] + 1]++;
+            if (Ai[p] != j) P.arowptr[j + 1]++;
+        }
+    for (int32_t i = 0; i < n; ++i) P.arowptr[i + 1] += P.arowptr[i];
+    P.acol.resize((size_t)P.arowptr[n]);
+    P.aval.resize((size_t)P.arowptr[n]);
+    {
+        std::vector<int64_t> fill(P.arowptr.begin(), P.arowptr.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = Ap[j]; p < Ap[j + 1]; ++p) {
+                const int32_t i = Ai[p];
+                P.acol[fill[i]] = j;
+                P.aval[fill[i]++] = p;
+                if (i != j) {
+                    P.acol[fill[j]] = i;
+                    P.aval[fill[j]++] = p;
+                }
+            }
+    }
+
     P.analyze_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SYM_OK;
 }
