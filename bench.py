@@ -50,6 +50,53 @@ def cpu_baseline(m: int = 48):
                       f"(n={w.n}, {f['flops']:.3e} flops, geometric ND), {dt:.1f} s"}
 
 
+def mixed_ir(dev, m: int = 80, reps: int = 3):
+    """Time to a normwise backward error <= 1e-12 on the mixed-precision
+    workload (3-D 27-point weighted Laplacian on an m^3 grid, weights
+    log-uniform in [1e-3, 1e3], diagonal = row sum * (1 + 1e-6), geometric
+    nested dissection): FP64 factor + solve (+ refinement if needed) against
+    FP32 factor + FP64 iterative refinement, both on this GPU."""
+    import numpy as np
+    import torch
+
+    import paper_1705_06575_amd as S
+    import workloads as W
+    w = W.config3(m)
+    Ax = torch.from_numpy(w.Ax).to(dev)
+    b = torch.from_numpy(W.dense_rhs(w.n, np.random.default_rng(20260003))).to(dev)
+    x = torch.empty_like(b)
+    out = {"workload": f"grid3d_27pt_{m}^3 weighted Laplacian (n={w.n}), geometric ND",
+           "tol": 1e-12}
+    for prec in ("f64", "f32"):
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision=prec)
+        an.bind(dev)
+        flops = an.stat("flops")
+        an.factor(Ax)
+        an.refine(Ax, b, tol=1e-12, maxit=50, out=x)      # warm-up
+        torch.cuda.synchronize()
+        times, tf = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            an.factor(Ax)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, iters, eta = an.refine(Ax, b, tol=1e-12, maxit=50, out=x)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t2 - t0) * 1e3)
+            tf.append((t1 - t0) * 1e3)
+        ms = float(np.median(times))
+        out[prec] = {"ms_to_1e-12": round(ms, 2), "factor_ms": round(float(np.median(tf)), 2),
+                     "refine_iters": iters, "eta_inf": eta,
+                     "gflops_fp64_equiv": round(flops / (ms * 1e-3) / 1e9, 1),
+                     "factor_gflops": round(flops / (float(np.median(tf)) * 1e-3) / 1e9, 1)}
+        out["factor_flops"] = flops
+        del an
+        torch.cuda.empty_cache()
+    out["speedup_mixed_vs_fp64"] = round(out["f64"]["ms_to_1e-12"] / out["f32"]["ms_to_1e-12"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +104,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=64, help="grid side (64 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP64 vs FP32+refinement comparison")
+    ap.add_argument("--mixed-m", type=int, default=80, help="grid side of the mixed-precision workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
@@ -189,6 +238,10 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
                      "traffic": None},
     }
+    if not args.no_mixed:
+        del an, rp
+        torch.cuda.empty_cache()
+        out["mixed_ir"] = mixed_ir(dev, args.mixed_m)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
