@@ -46,6 +46,40 @@ constexpr int NT = 256;           // threads per workgroup (4 wavefronts)
 constexpr int TR = kTileRows;     // tile rows (64)
 constexpr int LDC = TR + 1;       // LDS column stride of a tile
 
+// Copy the nr x w column-major block at src (leading dimension ld; nr, w
+// <= 64) into LDS (stride LDC) with all threads.  Thread t moves row t % 64
+// of columns t / 64 + 4u: every load is issued before the first store, so
+// the block costs one memory latency, and each column's rows are contiguous
+// across the wavefront.
+template <typename T>
+__device__ __forceinline__ void tile_in(T *dst, const T *__restrict__ src, int64_t ld, int nr, int w)
+{
+    const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        v[u] = (i < nr && c < w) ? src[(int64_t)c * ld + i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        if (i < nr && c < w) dst[c * LDC + i] = v[u];
+    }
+}
+
+// The reverse of tile_in: LDS block to global memory.
+template <typename T>
+__device__ __forceinline__ void tile_out(T *__restrict__ dst, const T *src, int64_t ld, int nr, int w)
+{
+    const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        if (i < nr && c < w) dst[(int64_t)c * ld + i] = src[c * LDC + i];
+    }
+}
+
 template <typename T>
 __global__ void k_fill_zero(T *__restrict__ x, int64_t count)
 {
@@ -309,10 +343,7 @@ __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
     const int w = J.w;
     T *LJ = Lx + J.valoff;
 
-    for (int idx = tid; idx < nr * w; idx += NT) {
-        const int i = idx % nr, c = idx / nr;
-        C[c * LDC + i] = LJ[(int64_t)c * J.ld + r0 + i];
-    }
+    tile_in(C, LJ + r0, J.ld, nr, w);
     __syncthreads();
 
     const int c_lo = 16 * wave, c_hi = c_lo + 16;
@@ -390,10 +421,7 @@ __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
 
     if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
 
-    for (int idx = tid; idx < nr * w; idx += NT) {
-        const int i = idx % nr, c = idx / nr;
-        LJ[(int64_t)c * J.ld + r0 + i] = C[c * LDC + i];
-    }
+    tile_out(LJ + r0, C, J.ld, nr, w);
 }
 
 // Internal (right-looking) update of one row tile of block J by the final
@@ -432,7 +460,9 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
                 for (int v = 0; v < 4; ++v) {
                     const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
                     const int col = 32 * wc + 16 * n + (lane & 15);
-                    if (row < nr && col < w) acc[m][n][v] = LJ[(int64_t)col * J.ld + r0 + row];
+                    const bool ok = row < nr && col < w;
+                    const T val = LJ[ok ? (int64_t)col * J.ld + r0 + row : 0];
+                    acc[m][n][v] = ok ? val : T(0);
                 }
         wave_product<T>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, T(-1), acc);
     }
@@ -451,10 +481,7 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
         }
         __syncthreads();
         panel_factor(C, nr, w, J.col0, info);
-        for (int idx = tid; idx < nr * w; idx += NT) {
-            const int i = idx % nr, c = idx / nr;
-            LJ[(int64_t)c * J.ld + r0 + i] = C[c * LDC + i];
-        }
+        tile_out(LJ + r0, C, J.ld, nr, w);
     } else if (active) {
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -487,14 +514,8 @@ __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
     const int nr = min(TR, J.r - r0);
     const int w = J.w;
     T *LJ = Lx + J.valoff;
-    for (int idx = tid; idx < w * w; idx += NT) {
-        const int i = idx % w, c = idx / w;
-        D[c * LDC + i] = LJ[(int64_t)c * J.ld + i];
-    }
-    for (int idx = tid; idx < nr * w; idx += NT) {
-        const int i = idx % nr, c = idx / nr;
-        X[c * LDC + i] = LJ[(int64_t)c * J.ld + r0 + i];
-    }
+    tile_in(D, LJ, J.ld, w, w);
+    tile_in(X, LJ + r0, J.ld, nr, w);
     __syncthreads();
     for (int c0 = 0; c0 < w; c0 += 16) {
         const int wb = min(16, w - c0);
@@ -506,10 +527,7 @@ __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
             __syncthreads();
         }
     }
-    for (int idx = tid; idx < nr * w; idx += NT) {
-        const int i = idx % nr, c = idx / nr;
-        LJ[(int64_t)c * J.ld + r0 + i] = X[c * LDC + i];
-    }
+    tile_out(LJ + r0, X, J.ld, nr, w);
 }
 
 inline unsigned grid_for(int64_t count, int per = 256)

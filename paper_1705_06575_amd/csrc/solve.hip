@@ -44,6 +44,51 @@ __device__ __forceinline__ double lane_value(double v, int src)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Stage the lower triangle of a w x w diagonal block (global, leading
+// dimension ld, columns from c0 on) into LDS as doubles.  All loads are
+// issued before the first store (one memory latency per block).
+template <typename T>
+__device__ __forceinline__ void stage_tri(double *D, const T *__restrict__ L, int64_t ld, int w,
+                                          int c0)
+{
+    const int i = threadIdx.x & 63, cq = threadIdx.x >> 6;
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = cq + 4 * u;
+        const bool ok = i < w && c < w && i >= c && c >= c0;
+        const T val = L[ok ? (int64_t)c * ld + i : 0];
+        v[u] = ok ? (double)val : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = cq + 4 * u;
+        if (i < w && c < w) D[c * LDT + i] = v[u];
+    }
+}
+
+// sum_{k = c0}^{w-1} L[k * ld + i] * ys[k] with the loads of 16 columns
+// issued together.
+template <typename T>
+__device__ __forceinline__ double row_dot(const T *__restrict__ L, int64_t ld, int64_t i,
+                                          const double *ys, int c0, int w)
+{
+    double s = 0.0;
+    for (int k0 = c0; k0 < w; k0 += 16) {
+        double lv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = k0 + j;
+            const T val = L[(k < w ? (int64_t)k * ld : 0) + i];
+            lv[j] = k < w ? (double)val : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (k0 + j < w) s += lv[j] * ys[k0 + j];
+    }
+    return s;
+}
+
 __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict__ perm,
                          double *__restrict__ y, int32_t n)
 {
@@ -93,10 +138,7 @@ __global__ __launch_bounds__(NT) void k_fwd(const SolveTask *__restrict__ tasks,
     const T *L = Lx + J.valoff;
     const int64_t ld = J.ld;
     const int w = J.w;
-    for (int idx = tid; idx < w * w; idx += NT) {
-        const int i = idx % w, c = idx / w;
-        if (i >= c && c >= c0) D[c * LDT + i] = (double)L[c * ld + i];
-    }
+    stage_tri(D, L, ld, w, c0);
     double v = 0.0;
     if (tid < 64 && tid >= c0 && tid < w) v = acc[J.col0 + tid];
     __syncthreads();
@@ -112,9 +154,9 @@ __global__ __launch_bounds__(NT) void k_fwd(const SolveTask *__restrict__ tasks,
     __syncthreads();
     const int i = w + tk.chunk * NT + tid;
     if (i < J.r) {
-        double s = 0.0;
-        for (int k = c0; k < w; ++k) s += (double)L[k * ld + i] * ys[k];
-        atomicAdd(&acc[rows[J.rowoff + i]], -s);
+        const int32_t row = rows[J.rowoff + i];
+        const double s = row_dot(L, ld, i, ys, c0, w);
+        atomicAdd(&acc[row], -s);
     }
 }
 
@@ -144,12 +186,29 @@ __global__ __launch_bounds__(NT) void k_bwd_gather(const SolveTask *__restrict__
     double part[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) part[q] = 0.0;
-    for (int i = i0 + lane; i < i1; i += 64) {
-        const double xr = x[rJ[i]];
+    // the chunk's four rows per lane: indices, then x values, then L
+    int32_t ri[4];
+    double xr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + 64 * u;
+        ri[u] = i < i1 ? rJ[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + 64 * u;
+        const double xv = x[ri[u]];
+        xr[u] = i < i1 ? xv : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + 64 * u;
+        const int ic = i < i1 ? i : i0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int k = wave + 4 * q;
-            if (k < w) part[q] += (double)L[k * ld + i] * xr;
+            const T val = L[(k < w ? (int64_t)k * ld : 0) + ic];
+            part[q] += (k < w ? (double)val : 0.0) * xr[u];
         }
     }
 #pragma unroll
@@ -176,10 +235,7 @@ __global__ __launch_bounds__(NT) void k_bwd_diag(const int32_t *__restrict__ blo
     const T *L = Lx + J.valoff;
     const int64_t ld = J.ld;
     const int w = J.w;
-    for (int idx = tid; idx < w * w; idx += NT) {
-        const int i = idx % w, c = idx / w;
-        if (i >= c) D[c * LDT + i] = (double)L[c * ld + i];
-    }
+    stage_tri(D, L, ld, w, 0);
     double v = 0.0;
     if (tid < w) v = x[J.col0 + tid];
     __syncthreads();
