@@ -162,18 +162,30 @@ __device__ __forceinline__ void wave_product(const T *__restrict__ pa, const T *
     const int ra0 = 32 * wr + li, ra1 = ra0 + 16;
     const int cb0 = 32 * wc + li, cb1 = cb0 + 16;
     const bool va0 = ra0 < nI, va1 = ra1 < nI, vb0 = cb0 < nJ, vb1 = cb1 < nJ;
-    for (int k0 = 0; k0 < wk; k0 += 4) {
-        const int k = k0 + lk;
-        const bool vk = k < wk;
-        const int64_t ko = (int64_t)k * ld;
-        const T a0 = (va0 && vk) ? sgn * pa[ra0 + ko] : T(0);
-        const T a1 = (va1 && vk) ? sgn * pa[ra1 + ko] : T(0);
-        const T b0 = (vb0 && vk) ? pb[cb0 + ko] : T(0);
-        const T b1 = (vb1 && vk) ? pb[cb1 + ko] : T(0);
-        acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+    // operands of eight k-steps (32 inner indices) are loaded together
+    for (int k0 = 0; k0 < wk; k0 += 32) {
+        T a0[8], a1[8], b0[8], b1[8];
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int k = k0 + 4 * st + lk;
+            const bool vk = k < wk;
+            const int64_t ko = vk ? (int64_t)k * ld : 0;
+            const T x0 = pa[(va0 ? ra0 : 0) + ko], x1 = pa[(va1 ? ra1 : 0) + ko];
+            const T y0 = pb[(vb0 ? cb0 : 0) + ko], y1 = pb[(vb1 ? cb1 : 0) + ko];
+            a0[st] = (va0 && vk) ? sgn * x0 : T(0);
+            a1[st] = (va1 && vk) ? sgn * x1 : T(0);
+            b0[st] = (vb0 && vk) ? y0 : T(0);
+            b1[st] = (vb1 && vk) ? y1 : T(0);
+        }
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            if (k0 + 4 * st < wk) {
+                acc[0][0] = Mfma<T>::mma(a0[st], b0[st], acc[0][0]);
+                acc[0][1] = Mfma<T>::mma(a0[st], b1[st], acc[0][1]);
+                acc[1][0] = Mfma<T>::mma(a1[st], b0[st], acc[1][0]);
+                acc[1][1] = Mfma<T>::mma(a1[st], b1[st], acc[1][1]);
+            }
+        }
     }
 }
 

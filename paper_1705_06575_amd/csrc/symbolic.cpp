@@ -453,7 +453,13 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     P.phases.clear();
     P.incs.clear();
     P.iptr.assign(1, 0);
-    struct RawInc { int32_t K, a0, a1, b0, b1; };
+    std::vector<int32_t> blk2ds((size_t)P.nb);
+    for (int32_t r = 0; r < P.nds; ++r)
+        for (int32_t b = P.sbptr[r]; b < P.sbptr[r + 1]; ++b) blk2ds[b] = r;
+    // K is a block; a descendant supernode's blocks share their rows below
+    // its columns, so all of its blocks' contributions to a tile form one
+    // product whose inner dimension is the supernode's width (wk)
+    struct RawInc { int32_t K, a0, a1, b0, b1, wk; };
     std::vector<std::vector<RawInc>> per_tile;
     P.imap.clear();
     auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags) {
@@ -477,7 +483,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         in.valoff = dK.valoff;
         in.mapoff = (int64_t)P.imap.size();
         in.ld = dK.ld;
-        in.wk = (int16_t)dK.w;
+        in.wk = (int16_t)ri.wk;
         in.b0 = ri.b0;
         in.a0 = ri.a0;
         in.nI = (uint8_t)(ri.b1 - ri.b0);
@@ -508,6 +514,9 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                 for (int64_t p = P.dptr[J]; p < P.dptr[J + 1]; ++p) {
                     const Pair &pr = P.pairs[p];
                     if (pr.K >= P.sbptr[s2]) break;     // internal pairs come last
+                    const int32_t ks = blk2ds[pr.K];
+                    if (pr.K != P.sbptr[ks]) continue;   // folded into the supernode's first block
+                    const int32_t kw = P.dsptr[ks + 1] - P.dsptr[ks];
                     const BlockDesc &dK = P.blk[pr.K];
                     const int32_t *rK = P.dsrows.data() + dK.rowoff;
                     int32_t pos = pr.a0;
@@ -516,7 +525,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                         const int32_t t = li / kTileRows;
                         const int32_t last = rJ[std::min((t + 1) * kTileRows, dJ.r) - 1];
                         const int32_t end = (int32_t)(std::upper_bound(rK + pos, rK + dK.r, last) - rK);
-                        per_tile[t].push_back(RawInc{pr.K, pr.a0, pr.a1, pos, end});
+                        per_tile[t].push_back(RawInc{pr.K, pr.a0, pr.a1, pos, end, kw});
                         pos = end;
                     }
                 }
