@@ -15,7 +15,8 @@
 struct sym_plan {
     sym::Plan P;
     size_t ws_bytes = 0;
-    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_incs = 0, off_imap = 0,
+    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_ibig = 0, off_incs = 0, off_imap = 0,
+           off_wptr = 0, off_witems = 0, off_wmap = 0,
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_info = 0;
@@ -58,8 +59,12 @@ void layout(sym_plan *h)
     h->off_rows = take(sizeof(int32_t) * P.dsrows.size());
     h->off_tasks = take(sizeof(sym::Task) * P.ftasks.size());
     h->off_iptr = take(sizeof(int64_t) * P.iptr.size());
+    h->off_ibig = take(sizeof(int64_t) * P.ibig.size());
     h->off_incs = take(sizeof(sym::Incidence) * P.incs.size());
     h->off_imap = take(P.imap.size());
+    h->off_wptr = take(sizeof(int64_t) * P.wptr.size());
+    h->off_witems = take(sizeof(sym::WaveItem) * P.witems.size());
+    h->off_wmap = take(P.wmap.size());
     h->off_lvl = take(sizeof(int32_t) * P.level_blocks.size());
     h->off_amap = take(sizeof(int64_t) * P.amap.size());
     h->off_perm = take(sizeof(int32_t) * P.perm.size());
@@ -146,8 +151,12 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.rows = (int32_t *)(base + h->off_rows);
     D.tasks = (sym::Task *)(base + h->off_tasks);
     D.iptr = (int64_t *)(base + h->off_iptr);
+    D.ibig = (int64_t *)(base + h->off_ibig);
     D.incs = (sym::Incidence *)(base + h->off_incs);
     D.imap = (uint8_t *)(base + h->off_imap);
+    D.wptr = (int64_t *)(base + h->off_wptr);
+    D.witems = (sym::WaveItem *)(base + h->off_witems);
+    D.wmap = (uint8_t *)(base + h->off_wmap);
     D.level_blocks = (int32_t *)(base + h->off_lvl);
     D.amap = (int64_t *)(base + h->off_amap);
     D.perm = (int32_t *)(base + h->off_perm);
@@ -166,8 +175,13 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
     if (e == hipSuccess) e = upload(D.tasks, P.ftasks.data(), sizeof(sym::Task) * P.ftasks.size(), s);
     if (e == hipSuccess) e = upload(D.iptr, P.iptr.data(), sizeof(int64_t) * P.iptr.size(), s);
+    if (e == hipSuccess) e = upload(D.ibig, P.ibig.data(), sizeof(int64_t) * P.ibig.size(), s);
     if (e == hipSuccess) e = upload(D.incs, P.incs.data(), sizeof(sym::Incidence) * P.incs.size(), s);
     if (e == hipSuccess) e = upload(D.imap, P.imap.data(), P.imap.size(), s);
+    if (e == hipSuccess) e = upload(D.wptr, P.wptr.data(), sizeof(int64_t) * P.wptr.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.witems, P.witems.data(), sizeof(sym::WaveItem) * P.witems.size(), s);
+    if (e == hipSuccess) e = upload(D.wmap, P.wmap.data(), P.wmap.size(), s);
     if (e == hipSuccess) e = upload(D.level_blocks, P.level_blocks.data(), sizeof(int32_t) * P.level_blocks.size(), s);
     if (e == hipSuccess) e = upload(D.amap, P.amap.data(), sizeof(int64_t) * P.amap.size(), s);
     if (e == hipSuccess) e = upload(D.perm, P.perm.data(), sizeof(int32_t) * P.perm.size(), s);

@@ -17,8 +17,12 @@ struct DevicePlan {
     int32_t *rows = nullptr;        // sum of supernode row counts
     Task *tasks = nullptr;          // factor tasks in launch order
     int64_t *iptr = nullptr;        // tasks+1: incidence ranges of external-update tasks
+    int64_t *ibig = nullptr;        // tasks: end of each task's leading large incidences
     Incidence *incs = nullptr;      // (tile, descendant) incidences
     uint8_t *imap = nullptr;        // their tile-relative rows and columns
+    int64_t *wptr = nullptr;        // 4*tasks+1: wavefront item ranges
+    WaveItem *witems = nullptr;     // small incidences per wavefront
+    uint8_t *wmap = nullptr;        // their tile-relative rows and columns
     int32_t *level_blocks = nullptr;// nb, grouped by level
     int64_t *amap = nullptr;        // nnzA
     int32_t *perm = nullptr;        // n

@@ -335,15 +335,276 @@ __device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int3
 // order (bitwise reproducible).  The next record is fetched one iteration
 // ahead.  With kFuseFactor the tile is tile 0 of a supernode's first block,
 // which is then factored in place.
+// Large incidences of one tile, by the whole workgroup: the product's
+// inner dimension is walked in chunks of 16 staged through double-buffered
+// LDS, each thread keeping the loads of the next two chunks in flight in
+// registers; wavefront (wr, wc) owns the 32 x 32 quadrant (wr, wc) of the
+// 64 x 64 product and subtracts it at the relative positions.  One barrier
+// per chunk.
 template <typename T>
+__device__ __forceinline__ void load_chunk(T (&va)[4], T (&vb)[4], const T *__restrict__ LK,
+                                           const Incidence &in, int kc)
+{
+    const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;
+    const int64_t ld = in.ld;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = kc + kq + 4 * j;
+        const bool vk = k < in.wk;
+        const int64_t ko = vk ? (int64_t)k * ld : 0;
+        const bool oa = vk && r < in.nI, ob = vk && r < in.nJ;
+        const T x = LK[in.b0 + (oa ? r : 0) + ko];
+        const T y = LK[in.a0 + (ob ? r : 0) + ko];
+        va[j] = oa ? x : T(0);
+        vb[j] = ob ? y : T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void coop_product(T *C, T (*As)[16][64], T (*Bs)[16][64], int32_t *s_rel,
+                                             const Incidence &in, const uint8_t *__restrict__ imap,
+                                             const T *__restrict__ Lx, int r0, int nr, int w)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int r = tid & 63, kq = tid >> 6;
+    const T *LK = Lx + in.valoff;
+    const int nI = in.nI, nJ = in.nJ;
+    const uint8_t *mp = imap + in.mapoff;
+    if (tid < 64) s_rel[tid] = tid < nI ? (int)mp[tid] : 0;
+    else if (tid < 128) s_rel[tid] = tid - 64 < nJ ? (int)mp[nI + tid - 64] : 0;
+    const int nch = (in.wk + 15) >> 4;
+    T pa[2][4], pb[2][4];
+    load_chunk(pa[0], pb[0], LK, in, 0);
+    if (nch > 1) load_chunk(pa[1], pb[1], LK, in, 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        As[0][kq + 4 * j][r] = pa[0][j];
+        Bs[0][kq + 4 * j][r] = pb[0][j];
+    }
+    if (nch > 2) load_chunk(pa[0], pb[0], LK, in, 32);
+    __syncthreads();
+    const bool active = 32 * wr < nI && 32 * wc < nJ;
+    typename Mfma<T>::acc_t acc[2][2] = {};
+    const int li = lane & 15;
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (active) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int kl = 4 * st + (lane >> 4);
+                const T a0 = As[buf][kl][32 * wr + li];
+                const T a1 = As[buf][kl][32 * wr + 16 + li];
+                const T b0 = Bs[buf][kl][32 * wc + li];
+                const T b1 = Bs[buf][kl][32 * wc + 16 + li];
+                acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
+                acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
+                acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
+                acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+            }
+        }
+        if (c + 1 < nch) {
+            // chunk c+1 sits in register stage (c+1) & 1; its buffer was last
+            // read in iteration c-1, before the previous barrier
+            const int rs = (c + 1) & 1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                As[buf ^ 1][kq + 4 * j][r] = pa[rs][j];
+                Bs[buf ^ 1][kq + 4 * j][r] = pb[rs][j];
+            }
+            if (c + 3 < nch) load_chunk(pa[rs], pb[rs], LK, in, 16 * (c + 3));
+        }
+        __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n2 = 0; n2 < 2; ++n2) {
+                const int col = 32 * wc + 16 * n2 + li;
+                const int Cc = s_rel[64 + (col < 64 ? col : 0)];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
+                    if (row < nI && col < nJ) {
+                        const int R = s_rel[row];
+                        if (R < nr && Cc < w && r0 + R >= Cc) C[Cc * LDC + R] -= acc[m][n2][v];
+                    }
+                }
+            }
+    }
+    __syncthreads();
+}
+
+// ---- wavefront items (small incidences)
+//
+// A wavefront runs its item list as one stream of operand batches.  A batch
+// covers kSteps k-steps of 4 (k = 4 (kb + s) + l / 16 for lane l): per step
+// four A values (product rows 16m + l % 16, m < 4) and one B value (product
+// column l % 16).  Addresses are clamped into the item's rows, columns and
+// k range, so every load is in bounds, none depends on another load's value
+// and every batch issues the same loads unconditionally (the hardware's
+// in-order load counter then lets the products of one batch wait for that
+// batch alone): the k range is masked at the product, and rows and columns
+// past the item's are dropped by the scatter.  The batch after the current
+// one is always in flight while the current one is multiplied (two register
+// sets used in turn), and the next item's record is fetched one item ahead.
+constexpr int kSteps = 4;
+
+// An item's record, read as whole dwords so that it can stay in scalar
+// registers.
+struct Item {
+    int64_t valoff, mapoff;
+    int ld, b0, a0, wk, nI, nJ;
+};
+
+__device__ __forceinline__ Item load_item(const WaveItem *__restrict__ items, int64_t i)
+{
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(items + i);
+    uint32_t x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = d[u];
+    Item it;
+    it.valoff = (int64_t)(((uint64_t)x[1] << 32) | x[0]);
+    it.mapoff = (int64_t)(((uint64_t)x[3] << 32) | x[2]);
+    it.ld = (int)x[4];
+    it.b0 = (int)x[5];
+    it.a0 = (int)x[6];
+    it.wk = (int)(int16_t)(x[7] & 0xffffu);
+    it.nI = (int)((x[7] >> 16) & 0xffu);
+    it.nJ = (int)(x[7] >> 24);
+    return it;
+}
+
+template <typename T>
+struct Batch {
+    T a[kSteps][4];
+    T b[kSteps];
+    int lr, cc;         // tile row of product row `lane`, tile column of product column lane % 16
+};
+
+__device__ __forceinline__ int item_nrb(const Item &it) { return (it.nI + 15) >> 4; }
+
+template <typename T>
+__device__ __forceinline__ void issue(Batch<T> &r, const T *__restrict__ Lx,
+                                      const uint8_t *__restrict__ wmap, const Item &it, int kb,
+                                      int lane)
+{
+    const T *LK = Lx + it.valoff;
+    const uint8_t *mp = wmap + it.mapoff;
+    const int li = lane & 15, kq = lane >> 4;
+    r.lr = mp[min(lane, it.nI - 1)];
+    r.cc = mp[it.nI + min(li, it.nJ - 1)];
+    // 32-bit element offsets from the (uniform) panel base: a panel holds
+    // far fewer than 2^29 entries
+    const uint32_t ld = (uint32_t)it.ld;
+    const int wk1 = it.wk - 1;
+    const uint32_t ob = (uint32_t)(it.a0 + min(li, it.nJ - 1));
+    const int nI1 = it.nI - 1;
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+        const uint32_t ko = (uint32_t)min(4 * (kb + s) + kq, wk1) * ld;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) r.a[s][m] = LK[(uint32_t)(it.b0 + min(16 * m + li, nI1)) + ko];
+        r.b[s] = LK[ob + ko];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void compute(const Batch<T> &r, typename Mfma<T>::acc_t (&acc)[4],
+                                        const Item &it, int kb, int lane)
+{
+    const int nrb = item_nrb(it);
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+        if (4 * (kb + s) < it.wk) {
+            const bool vk = 4 * (kb + s) + (lane >> 4) < it.wk;
+            const T b = vk ? r.b[s] : T(0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (m < nrb) acc[m] = Mfma<T>::mma(r.a[s][m], b, acc[m]);
+        }
+    }
+}
+
+// Subtract an item's finished product from the LDS tile and clear the
+// accumulators.  The tile row of product row i is lane i's lr; the tile
+// column of lane l's products is its own cc.
+template <typename T>
+__device__ __forceinline__ void scatter(T *C, typename Mfma<T>::acc_t (&acc)[4], const Batch<T> &r,
+                                        const Item &it, int r0, int nr, int w, int lane)
+{
+    const int nrb = item_nrb(it);
+    const int cc = r.cc;
+    const bool vc = (lane & 15) < it.nJ && cc < w;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (m < nrb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * m + Mfma<T>::row(lane, v);
+                const int R = __shfl(r.lr, row);
+                if (vc && row < it.nI && R < nr && r0 + R >= cc) C[cc * LDC + R] -= acc[m][v];
+            }
+        }
+        acc[m] = typename Mfma<T>::acc_t{};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ items,
+                                           const uint8_t *__restrict__ wmap,
+                                           const T *__restrict__ Lx, int64_t i0, int64_t i1, int r0,
+                                           int nr, int w)
+{
+    const int lane = threadIdx.x & 63;
+    Batch<T> X, Y;
+    typename Mfma<T>::acc_t acc[4] = {};
+    Item cur = load_item(items, i0);
+    int64_t inx = i0 + 1;                  // index of the prefetched record `nxt`
+    Item nxt = load_item(items, min(inx, i1 - 1));
+    int kb = 0;                            // first k-step of the batch being multiplied
+    issue(X, Lx, wmap, cur, 0, lane);
+    // multiply batch P (item cur, k-steps from kb) while the following batch
+    // loads into Q (after the last batch, a harmless reload); false once P
+    // was the last batch
+    auto step = [&](Batch<T> &P, Batch<T> &Q) -> bool {
+        const bool same = 4 * (kb + kSteps) < cur.wk;
+        const bool more = same || inx < i1;
+        const Item ni = same ? cur : nxt;
+        const int nkb = same ? kb + kSteps : 0;
+        issue(Q, Lx, wmap, ni, nkb, lane);
+        if (!same) {
+            ++inx;
+            nxt = load_item(items, min(inx, i1 - 1));
+        }
+        compute(P, acc, cur, kb, lane);
+        if (!same) scatter(C, acc, P, cur, r0, nr, w, lane);
+        cur = ni;
+        kb = nkb;
+        return more;
+    };
+    while (step(X, Y) && step(Y, X)) {
+    }
+}
+
+template <typename T, bool COOP>
 __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
                                                  const int64_t *__restrict__ iptr,
+                                                 const int64_t *__restrict__ ibig,
                                                  const Incidence *__restrict__ incs,
                                                  const uint8_t *__restrict__ imap,
+                                                 const int64_t *__restrict__ wptr,
+                                                 const WaveItem *__restrict__ witems,
+                                                 const uint8_t *__restrict__ wmap,
                                                  const BlockDesc *__restrict__ blk,
                                                  T *__restrict__ Lx, int32_t *__restrict__ info)
 {
     __shared__ T C[64 * LDC];
+    __shared__ T As[COOP ? 2 : 1][16][64];
+    __shared__ T Bs[COOP ? 2 : 1][16][64];
+    __shared__ int32_t s_rel[COOP ? 128 : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -358,77 +619,23 @@ __global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
     tile_in(C, LJ + r0, J.ld, nr, w);
     __syncthreads();
 
-    const int c_lo = 16 * wave, c_hi = c_lo + 16;
     int64_t q = iptr[blockIdx.x];
-    const int64_t qend = iptr[blockIdx.x + 1];
-    if (c_lo < w && q < qend) {
-        Incidence nxt = incs[q];
-        for (; q < qend; ++q) {
-            const Incidence in = nxt;
-            if (q + 1 < qend) nxt = incs[q + 1];
-            if (in.cmax < c_lo || in.cmin >= c_hi) continue;
-            const int nI = in.nI, nJ = in.nJ;
-            const uint8_t *mp = imap + in.mapoff;
-            // relative indices: lane l holds tile row l and tile column l
-            const int lrl = lane < nI ? (int)mp[lane] : 0;
-            const int lcl = lane < nJ ? (int)mp[nI + lane] : 255;
-            const int jlo = __popcll(__ballot(lcl < c_lo));
-            const int jhi = __popcll(__ballot(lcl < c_hi));
-            if (jlo >= jhi) continue;
-            const int jb = jlo + (lane & 15);
-            const bool vb = jb < jhi;
-            const int colC = __shfl(lcl, vb ? jb : 0);
-            const int nrb = (nI + 15) >> 4;
-            const T *LK = Lx + in.valoff;
-            const int64_t ld = in.ld;
-            const int wk = in.wk;
-            typename Mfma<T>::acc_t acc[4] = {};
-            // one k-step of operands is fetched ahead of the products
-            T b_nx, a_nx[4];
-            {
-                const int k = lane >> 4;
-                const bool vk = k < wk;
-                b_nx = (vb && vk) ? LK[in.a0 + jb + (int64_t)k * ld] : T(0);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int ar = 16 * m + (lane & 15);
-                    a_nx[m] = (ar < nI && vk) ? LK[in.b0 + ar + (int64_t)k * ld] : T(0);
-                }
+    if constexpr (COOP) {
+        const int64_t qb = ibig[blockIdx.x];
+        for (; q < qb; ++q) {
+            const Incidence in = incs[q];
+            if (in.nI > nr || in.nJ > w) {       // corrupt plan: never write outside the tile
+                if (tid == 0) atomicMin(info + 1, tk.J);
+                continue;
             }
-            for (int k0 = 0; k0 < wk; k0 += 4) {
-                const T b = b_nx;
-                T a[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) a[m] = a_nx[m];
-                {
-                    const int k = k0 + 4 + (lane >> 4);
-                    const bool vk = k < wk;
-                    const int64_t ko = (int64_t)k * ld;
-                    b_nx = (vb && vk) ? LK[in.a0 + jb + ko] : T(0);
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int ar = 16 * m + (lane & 15);
-                        a_nx[m] = (m < nrb && ar < nI && vk) ? LK[in.b0 + ar + ko] : T(0);
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    if (m < nrb) acc[m] = Mfma<T>::mma(a[m], b, acc[m]);
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                if (m < nrb) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = 16 * m + Mfma<T>::row(lane, v);
-                        const int R = __shfl(lrl, row);
-                        if (vb && row < nI && R < nr && colC < w && r0 + R >= colC)
-                            C[colC * LDC + R] -= acc[m][v];
-                    }
-                }
-            }
+            coop_product(C, As, Bs, s_rel, in, imap, Lx, r0, nr, w);
         }
     }
+
+    // the small incidences: each wavefront runs its own item list
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int64_t i0 = wptr[4 * blockIdx.x + wv], i1 = wptr[4 * blockIdx.x + wv + 1];
+    if (i0 < i1) wave_items(C, witems, wmap, (const T *)Lx, i0, i1, r0, nr, w);
     __syncthreads();
 
     if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
@@ -586,9 +793,14 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
     for (const Phase &ph : P.phases) {
         const unsigned g = (unsigned)(ph.t1 - ph.t0);
         Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
-        if (ph.kind == kPhaseExternal)
-            k_external<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.incs, D.imap, D.blk, Lx,
-                                           D.info);
+        if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
+            k_external<T, true><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
+                                                 D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
+                                                 D.wmap, D.blk, Lx, D.info);
+        else if (ph.kind == kPhaseExternal)
+            k_external<T, false><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
+                                                  D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
+                                                  D.wmap, D.blk, Lx, D.info);
         else if (ph.kind == kPhaseInternal)
             k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info);
         else

@@ -59,10 +59,32 @@ struct Incidence {      // 40 bytes, device-visible
     uint8_t pad[6];
 };
 
+// The same contribution as one wavefront sees it.  Wavefront v of a tile's
+// workgroup owns the tile's columns [16v, 16v + 16); for every incidence
+// that meets them it gets an item: the product rows are K's local rows
+// [b0, b0 + nI), the product columns K's local rows [a0, a0 + nJ) (those
+// landing in the wavefront's columns, nJ <= 16).  wmap[mapoff ...] holds
+// the nI tile-relative rows, then the nJ tile columns.
+struct WaveItem {       // 32 bytes, device-visible
+    int64_t valoff;     // K's panel offset
+    int64_t mapoff;     // offset into the wavefront map
+    int32_t ld;         // K's leading dimension
+    int32_t b0;
+    int32_t a0;
+    int16_t wk;         // K's width (inner dimension)
+    uint8_t nI, nJ;
+};
+
 static_assert(sizeof(Incidence) == 40, "Incidence layout is shared with the device");
+static_assert(sizeof(WaveItem) == 32, "WaveItem layout is shared with the device");
 static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
 constexpr int32_t kFuseFactor = 1;
+
+// An incidence is "large" -- multiplied by the whole workgroup through LDS
+// -- when its product has at least this many rows, columns and inner
+// indices.
+constexpr int32_t kLargeRows = 32, kLargeCols = 32, kLargeInner = 32;
 
 // One kernel launch of the factorization.
 enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2 };
@@ -142,8 +164,15 @@ struct Plan {
     std::vector<Task> ftasks;       // all factor tasks in launch order
     std::vector<Phase> phases;      // launches
     std::vector<int64_t> iptr;      // ftasks.size()+1: incidences of external-update tasks
+    std::vector<int64_t> ibig;      // ftasks.size(): end of each task's leading large incidences
+    std::vector<uint8_t> phase_coop;// per phase: an external phase with large incidences
     std::vector<Incidence> incs;
     std::vector<uint8_t> imap;      // tile-relative rows and columns of every incidence
+    // the remaining (small) incidences as per-wavefront items: wavefront v of
+    // task q runs items [wptr[4q + v], wptr[4q + v + 1])
+    std::vector<int64_t> wptr;      // 4 * ftasks.size() + 1
+    std::vector<WaveItem> witems;
+    std::vector<uint8_t> wmap;
     // arithmetic of each launch kind by the method's count (lower-triangle
     // products, one flop per multiply, add, divide and square root):
     // [0] scatter (none), [1] external, [2] trsm, [3] internal; the four sum

@@ -462,9 +462,62 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     struct RawInc { int32_t K, a0, a1, b0, b1, wk; };
     std::vector<std::vector<RawInc>> per_tile;
     P.imap.clear();
-    auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags) {
+    P.ibig.clear();
+    P.wptr.assign(1, 0);
+    P.witems.clear();
+    P.wmap.clear();
+    // tasks without wavefront items push their (empty) ranges here
+    auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags, int64_t big_end) {
         P.ftasks.push_back(Task{J, t, K, flags});
         P.iptr.push_back((int64_t)P.incs.size());
+        P.ibig.push_back(big_end);
+        while ((int64_t)P.wptr.size() < 4 * (int64_t)P.ftasks.size() + 1)
+            P.wptr.push_back((int64_t)P.witems.size());
+    };
+    // tile rows of K's rows [b0, b1) and tile columns of K's rows [a0, a1)
+    std::vector<uint8_t> rrel, crel;
+    auto relative = [&](int32_t J, int32_t t, const RawInc &ri) {
+        const BlockDesc &dJ = P.blk[J];
+        const BlockDesc &dK = P.blk[ri.K];
+        const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
+        const int32_t *rK = P.dsrows.data() + dK.rowoff;
+        const int32_t r0 = t * kTileRows;
+        const int32_t nr = std::min(kTileRows, dJ.r - r0);
+        rrel.clear();
+        crel.clear();
+        int32_t p = r0;
+        for (int32_t q = ri.b0; q < ri.b1; ++q) {
+            while (p < r0 + nr && rJ[p] < rK[q]) ++p;
+            rrel.push_back((uint8_t)(p - r0));
+        }
+        for (int32_t q = ri.a0; q < ri.a1; ++q) crel.push_back((uint8_t)(rK[q] - dJ.col0));
+    };
+    // the wavefront items of one task's small incidences, wavefront-major
+    auto emit_wave_items = [&](int32_t J, int32_t t, const std::vector<const RawInc *> &small) {
+        for (int32_t v = 0; v < 4; ++v) {
+            for (const RawInc *ri : small) {
+                relative(J, t, *ri);
+                // columns are increasing: the wavefront's are a contiguous run
+                int32_t jlo = 0, jhi = 0;
+                while (jlo < (int32_t)crel.size() && crel[jlo] < 16 * v) ++jlo;
+                jhi = jlo;
+                while (jhi < (int32_t)crel.size() && crel[jhi] < 16 * v + 16) ++jhi;
+                if (jlo == jhi) continue;
+                WaveItem it{};
+                it.valoff = P.blk[ri->K].valoff;
+                it.mapoff = (int64_t)P.wmap.size();
+                it.ld = P.blk[ri->K].ld;
+                it.b0 = ri->b0;
+                it.a0 = ri->a0 + jlo;
+                it.wk = (int16_t)ri->wk;
+                it.nI = (uint8_t)rrel.size();
+                it.nJ = (uint8_t)(jhi - jlo);
+                P.wmap.insert(P.wmap.end(), rrel.begin(), rrel.end());
+                P.wmap.insert(P.wmap.end(), crel.begin() + jlo, crel.begin() + jhi);
+                P.witems.push_back(it);
+            }
+            P.wptr.push_back((int64_t)P.witems.size());
+        }
     };
     auto open_phase = [&](int32_t kind) { P.phases.push_back(Phase{kind, (int64_t)P.ftasks.size(), 0}); };
     auto close_phase = [&]() {
@@ -499,6 +552,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         in.cmax = (uint8_t)(rK[ri.a1 - 1] - dJ.col0);
         P.incs.push_back(in);
     };
+    std::vector<const RawInc *> small;
     for (int32_t l = 0; l < P.nslevels; ++l) {
         int32_t maxnb = 0;
         open_phase(kPhaseExternal);
@@ -533,8 +587,19 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                 for (int32_t t = 0; t < nt; ++t) {
                     const bool fuse = first && t == 0;
                     if (per_tile[t].empty() && !fuse) continue;
-                    for (const RawInc &ri : per_tile[t]) emit_inc(J, t, ri);
-                    push_task(J, t, -1, fuse ? kFuseFactor : 0);
+                    // large incidences first, then the rest (each keeps list order)
+                    auto large = [](const RawInc &ri) {
+                        return ri.b1 - ri.b0 >= kLargeRows && ri.a1 - ri.a0 >= kLargeCols &&
+                               ri.wk >= kLargeInner;
+                    };
+                    small.clear();
+                    for (const RawInc &ri : per_tile[t]) {
+                        if (large(ri)) emit_inc(J, t, ri);
+                        else small.push_back(&ri);
+                    }
+                    const int64_t big_end = (int64_t)P.incs.size();
+                    emit_wave_items(J, t, small);
+                    push_task(J, t, -1, fuse ? kFuseFactor : 0, big_end);
                 }
             }
         }
@@ -542,7 +607,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         open_phase(kPhaseTrsm);
         for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
             const int32_t J = P.sbptr[sl_list[q]];
-            for (int32_t t = 1; t < ntiles(J); ++t) push_task(J, t, -1, 0);
+            for (int32_t t = 1; t < ntiles(J); ++t) push_task(J, t, -1, 0, 0);
         }
         close_phase();
         for (int32_t k = 1; k < maxnb; ++k) {
@@ -553,7 +618,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                 if (nbs <= k) continue;
                 for (int32_t c = k; c < nbs; ++c)
                     for (int32_t t = 0; t < ntiles(b0 + c); ++t)
-                        push_task(b0 + c, t, b0 + k - 1, (c == k && t == 0) ? kFuseFactor : 0);
+                        push_task(b0 + c, t, b0 + k - 1, (c == k && t == 0) ? kFuseFactor : 0, 0);
             }
             close_phase();
             open_phase(kPhaseTrsm);
@@ -561,10 +626,18 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                 const int32_t s2 = sl_list[q];
                 const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
                 if (nbs <= k) continue;
-                for (int32_t t = 1; t < ntiles(b0 + k); ++t) push_task(b0 + k, t, -1, 0);
+                for (int32_t t = 1; t < ntiles(b0 + k); ++t) push_task(b0 + k, t, -1, 0, 0);
             }
             close_phase();
         }
+    }
+
+    // external phases with large incidences use the cooperative kernel
+    P.phase_coop.assign(P.phases.size(), 0);
+    for (size_t ph = 0; ph < P.phases.size(); ++ph) {
+        if (P.phases[ph].kind != kPhaseExternal) continue;
+        for (int64_t q = P.phases[ph].t0; q < P.phases[ph].t1; ++q)
+            if (P.ibig[q] > P.iptr[q]) { P.phase_coop[ph] = 1; break; }
     }
 
     // ----------------------------------- arithmetic per launch kind
