@@ -20,7 +20,8 @@
 //                does no searching in global memory.  Tile 0 of each
 //                supernode's first block then factors that block in LDS.
 //   k_trsm     : the remaining row tiles of a just-factored block solve
-//                X := X L_JJ^{-T}.
+//                X := X L_JJ^{-T} (16 x 16 diagonal triangles inverted, the
+//                rest on matrix cores).
 //   k_internal : right-looking updates inside a wide supernode: once block
 //                k-1 is final, every tile of blocks k, k+1, ... subtracts
 //                its product with block k-1 (matrix cores, accumulators
@@ -65,6 +66,29 @@ __device__ __forceinline__ void tile_in(T *dst, const T *__restrict__ src, int64
     for (int u = 0; u < 16; ++u) {
         const int c = c0 + 4 * u;
         if (i < nr && c < w) dst[c * LDC + i] = v[u];
+    }
+}
+
+// Two blocks of the same panel (rows [0, n1) at s1 and [0, n2) at s2, w
+// columns each) into LDS with all loads issued before the first store; the
+// rest of both 64 x 64 LDS blocks is set to zero.
+template <typename T>
+__device__ __forceinline__ void tile2_in(T *d1, const T *__restrict__ s1, int n1, T *d2,
+                                         const T *__restrict__ s2, int n2, int64_t ld, int w)
+{
+    const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+    T v[16], u2[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        v[u] = (i < n1 && c < w) ? s1[(int64_t)c * ld + i] : T(0);
+        u2[u] = (i < n2 && c < w) ? s2[(int64_t)c * ld + i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        d1[c * LDC + i] = v[u];
+        d2[c * LDC + i] = u2[u];
     }
 }
 
@@ -202,13 +226,35 @@ __device__ __forceinline__ float lane_value(float v, int src)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// Reciprocal square root of a pivot: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - d y^2) / 2 (a few ulp; a non-positive or NaN
+// pivot gives NaN or infinity, and the pivot check reports it).
+__device__ __forceinline__ double pivot_rsqrt(double d)
+{
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-d * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float pivot_rsqrt(float d)
+{
+    float y = __builtin_amdgcn_rsqf(d);
+    const float e = fmaf(-d * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+}
+
 // One wavefront factors the 16-column sub-panel C[c0 : nr, c0 : c0 + wb]
 // (LDS, column-major, stride LDC) in place: lane i holds row c0 + i in
-// registers.  Column k: the pivot's square root, the division of the rows
-// below it, and the rank-1 update of the sub-panel's later columns, with the
-// needed entries of other rows read across lanes (no barriers).  Rows
-// c0 .. c0 + wb - 1 form the diagonal block (Cholesky); the rows below get
-// the triangular solve against it.
+// registers.  Column k: the pivot's reciprocal square root r (the diagonal
+// entry is d r), the scaling of the rows below it by r, and the rank-1 update of the sub-panel's later
+// columns, with the needed entries of other rows read across lanes (no
+// barriers).  Rows c0 .. c0 + wb - 1 form the diagonal block (Cholesky);
+// the rows below get the triangular solve against it.  All 16 columns run
+// without branches; columns past wb start at zero, never feed the real ones
+// (only later columns depend on a column) and are not stored.
 template <typename T>
 __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
                                               int32_t *info)
@@ -221,19 +267,14 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
     for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? C[(c0 + c) * LDC + row] : T(0);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        if (k < wb) {
-            const T d = lane_value(r[k], k);
-            const T l = sqrt(d);
-            if (lane == 0 && !(d > T(0))) atomicMin(info, col0 + c0 + k);
-            if (lane == k) r[k] = l;
-            else if (lane > k) r[k] = r[k] / l;
+        const T d = lane_value(r[k], k);
+        if (k < wb && !(d > T(0)) && lane == 0) atomicMin(info, col0 + c0 + k);
+        const T inv = pivot_rsqrt(d);
+        r[k] = lane == k ? d * inv : (lane > k ? r[k] * inv : r[k]);
 #pragma unroll
-            for (int c = k + 1; c < 16; ++c) {
-                if (c < wb) {
-                    const T lck = lane_value(r[k], c);
-                    if (lane >= c) r[c] -= r[k] * lck;
-                }
-            }
+        for (int c = k + 1; c < 16; ++c) {
+            const T lck = lane_value(r[k], c);
+            r[c] = lane >= c ? r[c] - r[k] * lck : r[c];
         }
     }
 #pragma unroll
@@ -241,29 +282,76 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
         if (mine && c < wb) C[(c0 + c) * LDC + row] = r[c];
 }
 
-// One wavefront solves X[:, c0 : c0 + wb] := X[:, c0 : c0 + wb] D^{-T} for the
-// wb x wb lower triangle D = L[c0 : c0 + wb, c0 : c0 + wb] (both LDS,
-// column-major, stride LDC), lane i owning row i of X (nr <= 64 rows).
+// One wavefront inverts the wb x wb lower triangle D[c0 .., c0 ..] (LDS,
+// column-major, stride LDC; wb <= 16, and D is zero outside its w x w
+// block), padded to 16 x 16 with the identity:
+// lane j < 16 forms column j of the inverse by forward substitution, the
+// triangle's entries being read as LDS broadcasts.  The result goes to M
+// (M[c * 17 + k] = inverse[c][k]).
 template <typename T>
-__device__ __forceinline__ void wave_subsolve(T *X, const T *L, int c0, int wb, int nr)
+__device__ __forceinline__ void wave_tri_inverse(const T *D, int c0, int wb, T *M)
 {
     const int lane = threadIdx.x & 63;
-    const bool mine = lane < nr;
-    T x[16];
+    const int j = lane & 15;
+    T m[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) x[c] = (mine && c < wb) ? X[(c0 + c) * LDC + lane] : T(0);
+    for (int i = 0; i < 16; ++i) {
+        T s0 = i == j ? T(1) : T(0), s1 = T(0);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        if (c < wb) {
-            T acc = x[c];
-#pragma unroll
-            for (int k = 0; k < c; ++k) acc -= x[k] * L[(c0 + k) * LDC + c0 + c];
-            x[c] = acc / L[(c0 + c) * LDC + c0 + c];
+        for (int k = 0; k < i; ++k) {
+            const T lik = D[(c0 + k) * LDC + c0 + i];
+            if (k & 1) s1 -= lik * m[k];
+            else s0 -= lik * m[k];
         }
+        const T dii = D[(c0 + i) * LDC + c0 + i];
+        m[i] = (s0 + s1) / (i < wb ? dii : T(1));
     }
+    if (lane < 16) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-        if (mine && c < wb) X[(c0 + c) * LDC + lane] = x[c];
+        for (int i = 0; i < 16; ++i) M[i * 17 + j] = m[i];
+    }
+}
+
+// One wavefront solves rows [rw, rw + 16) of X := X D^{-T} (X: nr x w tile,
+// D: the w x w factored diagonal block, both LDS column-major with stride
+// LDC) one 16-column block at a time with matrix cores: block j is
+// (X_j - sum_{i<j} X_i D_ji^T) Minv_j^T, Minv_j the inverted diagonal block
+// j (M + 272 j).  A wavefront touches only its own rows, so the blocks need
+// no barriers: its LDS writes are ordered before its later reads.
+template <typename T>
+__device__ __forceinline__ void wave_rows_solve(T *X, const T *D, const T *M, int rw, int w)
+{
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, kq = lane >> 4;
+    for (int cb = 0; cb < w; cb += 16) {
+        typename Mfma<T>::acc_t acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = X[(cb + li) * LDC + rw + Mfma<T>::row(lane, v)];
+        for (int ib = 0; ib < cb; ib += 16) {
+#pragma unroll
+            for (int ks = 0; ks < 16; ks += 4) {
+                const T a = X[(ib + ks + kq) * LDC + rw + li];
+                const T b = D[(ib + ks + kq) * LDC + cb + li];
+                acc = Mfma<T>::mma(-a, b, acc);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[(cb + li) * LDC + rw + Mfma<T>::row(lane, v)] = acc[v];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const T *Mj = M + 272 * (cb >> 4);
+        typename Mfma<T>::acc_t y = {};
+#pragma unroll
+        for (int ks = 0; ks < 16; ks += 4) {
+            const T a = X[(cb + ks + kq) * LDC + rw + li];
+            const T b = Mj[li * 17 + ks + kq];
+            y = Mfma<T>::mma(a, b, y);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[(cb + li) * LDC + rw + Mfma<T>::row(lane, v)] = y[v];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // C[ra:nr, ca:w] -= X[ra:nr, k0:k0+kw] * Y[ca:w, k0:k0+kw]^T in 16 x 16
@@ -716,9 +804,10 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
 }
 
 // Row tile t >= 1 of block J solves X := X L_JJ^{-T} against J's factored
-// diagonal block, blocked by 16 columns: one wavefront substitutes a
-// 16-column slice (rows in lanes), then all four wavefronts subtract its
-// product with the diagonal block's rows from the later columns.
+// diagonal block, blocked by 16 columns: the four wavefronts first invert
+// one 16 x 16 diagonal triangle each, then each solves 16 of the tile's rows
+// through all column blocks with matrix-core products (no barriers).  The
+// zero padding of both LDS blocks keeps the padded lanes finite.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
                                              const BlockDesc *__restrict__ blk,
@@ -726,26 +815,22 @@ __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
 {
     __shared__ T D[64 * LDC];
     __shared__ T X[64 * LDC];
+    __shared__ T M[4 * 272];
     const int tid = threadIdx.x;
+    const int wave = tid >> 6;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc J = blk[tk.J];
     const int r0 = tk.t * TR;
     const int nr = min(TR, J.r - r0);
     const int w = J.w;
     T *LJ = Lx + J.valoff;
-    tile_in(D, LJ, J.ld, w, w);
-    tile_in(X, LJ + r0, J.ld, nr, w);
+    tile2_in(D, LJ, w, X, LJ + r0, nr, J.ld, w);
     __syncthreads();
-    for (int c0 = 0; c0 < w; c0 += 16) {
-        const int wb = min(16, w - c0);
-        if ((tid >> 6) == 0) wave_subsolve(X, D, c0, wb, nr);
-        __syncthreads();
-        if (c0 + wb < w) {
-            // X[:, c0+wb:w] -= X[:, c0:c0+wb] * D[c0+wb:w, c0:c0+wb]^T (all rows)
-            block_update(X, X, D, 0, nr, c0 + wb, w, c0, wb, 64);
-            __syncthreads();
-        }
-    }
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    if (16 * wv < w) wave_tri_inverse(D, 16 * wv, min(16, w - 16 * wv), M + 272 * wv);
+    __syncthreads();
+    if (16 * wv < nr) wave_rows_solve(X, D, M, 16 * wv, w);
+    __syncthreads();
     tile_out(LJ + r0, X, J.ld, nr, w);
 }
 
