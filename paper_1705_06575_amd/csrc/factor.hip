@@ -213,6 +213,49 @@ __device__ __forceinline__ void wave_product(const T *__restrict__ pa, const T *
     }
 }
 
+// acc[m][n] -= A[rows, :] * B[cols, :]^T for the 32 x 32 quadrant (wr, wc)
+// of a product with inner dimension wk <= 64, rows and columns as in
+// wave_product.  All operand loads are issued before the first product
+// (addresses clamped into the valid range, invalid k masked at the
+// product), so the whole update costs one memory latency.
+template <typename T>
+__device__ __forceinline__ void wave_product_all(const T *__restrict__ pa, const T *__restrict__ pb,
+                                                 int64_t ld, int nI, int nJ, int wk, int wr, int wc,
+                                                 typename Mfma<T>::acc_t (&acc)[2][2])
+{
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    // 32-bit byte offsets from the uniform panel pointers (a panel is far
+    // below 4 GiB), so the loads take the scalar-base addressing form
+    const uint32_t ra0 = sizeof(T) * min(32 * wr + li, nI - 1);
+    const uint32_t ra1 = sizeof(T) * min(32 * wr + 16 + li, nI - 1);
+    const uint32_t cb0 = sizeof(T) * min(32 * wc + li, nJ - 1);
+    const uint32_t cb1 = sizeof(T) * min(32 * wc + 16 + li, nJ - 1);
+    const uint32_t ldb = sizeof(T) * (uint32_t)ld;
+    const char *ca = reinterpret_cast<const char *>(pa);
+    const char *cbp = reinterpret_cast<const char *>(pb);
+    T a0[16], a1[16], b0[16], b1[16];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+        const uint32_t ko = (uint32_t)min(4 * st + lk, wk - 1) * ldb;
+        a0[st] = *reinterpret_cast<const T *>(ca + (ra0 + ko));
+        a1[st] = *reinterpret_cast<const T *>(ca + (ra1 + ko));
+        b0[st] = *reinterpret_cast<const T *>(cbp + (cb0 + ko));
+        b1[st] = *reinterpret_cast<const T *>(cbp + (cb1 + ko));
+    }
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+        if (4 * st < wk) {
+            const bool vk = 4 * st + lk < wk;
+            const T x0 = vk ? -a0[st] : T(0), x1 = vk ? -a1[st] : T(0);
+            acc[0][0] = Mfma<T>::mma(x0, b0[st], acc[0][0]);
+            acc[0][1] = Mfma<T>::mma(x0, b1[st], acc[0][1]);
+            acc[1][0] = Mfma<T>::mma(x1, b0[st], acc[1][0]);
+            acc[1][1] = Mfma<T>::mma(x1, b1[st], acc[1][1]);
+        }
+    }
+}
+
 // Value of v in lane `src` (a compile-time or wave-uniform lane index).
 __device__ __forceinline__ double lane_value(double v, int src)
 {
@@ -276,6 +319,9 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
             const T lck = lane_value(r[k], c);
             r[c] = lane >= c ? r[c] - r[k] * lck : r[c];
         }
+        // columns form a dependence chain anyway; keeping each column's
+        // cross-lane reads together bounds the scalar registers they use
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c)
@@ -584,18 +630,21 @@ __device__ __forceinline__ void issue(Batch<T> &r, const T *__restrict__ Lx,
     const int li = lane & 15, kq = lane >> 4;
     r.lr = mp[min(lane, it.nI - 1)];
     r.cc = mp[it.nI + min(li, it.nJ - 1)];
-    // 32-bit element offsets from the (uniform) panel base: a panel holds
-    // far fewer than 2^29 entries
-    const uint32_t ld = (uint32_t)it.ld;
+    // 32-bit byte offsets from the uniform panel base (a panel is far below
+    // 4 GiB), so the loads take the scalar-base addressing form
+    const char *base = reinterpret_cast<const char *>(LK);
+    const uint32_t ldb = sizeof(T) * (uint32_t)it.ld;
     const int wk1 = it.wk - 1;
-    const uint32_t ob = (uint32_t)(it.a0 + min(li, it.nJ - 1));
-    const int nI1 = it.nI - 1;
+    const uint32_t ob = sizeof(T) * (uint32_t)(it.a0 + min(li, it.nJ - 1));
+    uint32_t oa[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) oa[m] = sizeof(T) * (uint32_t)(it.b0 + min(16 * m + li, it.nI - 1));
 #pragma unroll
     for (int s = 0; s < kSteps; ++s) {
-        const uint32_t ko = (uint32_t)min(4 * (kb + s) + kq, wk1) * ld;
+        const uint32_t ko = (uint32_t)min(4 * (kb + s) + kq, wk1) * ldb;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) r.a[s][m] = LK[(uint32_t)(it.b0 + min(16 * m + li, nI1)) + ko];
-        r.b[s] = LK[ob + ko];
+        for (int m = 0; m < 4; ++m) r.a[s][m] = *reinterpret_cast<const T *>(base + (oa[m] + ko));
+        r.b[s] = *reinterpret_cast<const T *>(base + (ob + ko));
     }
 }
 
@@ -678,7 +727,7 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
 }
 
 template <typename T, bool COOP>
-__global__ __launch_bounds__(NT) void k_external(const Task *__restrict__ tasks,
+__global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__restrict__ tasks,
                                                  const int64_t *__restrict__ iptr,
                                                  const int64_t *__restrict__ ibig,
                                                  const Incidence *__restrict__ incs,
@@ -759,6 +808,10 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
 
     typename Mfma<T>::acc_t acc[2][2] = {};
     if (active) {
+        // the tile's entries seed the accumulators (32-bit byte offsets
+        // from the tile's first entry; clamped, then masked)
+        const char *tb = reinterpret_cast<const char *>(LJ + r0);
+        const uint32_t ldb = sizeof(T) * (uint32_t)J.ld;
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -768,10 +821,11 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
                     const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
                     const int col = 32 * wc + 16 * n + (lane & 15);
                     const bool ok = row < nr && col < w;
-                    const T val = LJ[ok ? (int64_t)col * J.ld + r0 + row : 0];
+                    const uint32_t off = (uint32_t)min(col, w - 1) * ldb + sizeof(T) * (uint32_t)min(row, nr - 1);
+                    const T val = *reinterpret_cast<const T *>(tb + off);
                     acc[m][n][v] = ok ? val : T(0);
                 }
-        wave_product<T>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, T(-1), acc);
+        wave_product_all<T>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
     }
     if (tk.flags & kFuseFactor) {
         if (active) {
