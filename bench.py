@@ -97,6 +97,82 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
     return out
 
 
+FACTOR_SOURCE = os.path.join(ROOT, "paper_1705_06575_amd", "csrc", "factor.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_factor_grid3d_7pt_64.json")
+FACTOR_KERNELS = ("k_external", "k_internal", "k_trsm")
+
+
+def _source_digest() -> str:
+    import hashlib
+    with open(FACTOR_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def copy_probe(nbytes: int, reps: int = 3):
+    """A plain device copy of known size: the calibration run for the HBM
+    byte counters (each counter is scaled by what it reads for this copy)."""
+    import torch
+    n = nbytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "reps": reps}))
+
+
+def _counter_rows(path: str, counter: str):
+    """(kernel name, value) per dispatch of a rocprofv3 counter CSV."""
+    import csv
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def write_traffic(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str,
+                  copy_bytes: int, out_path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of each factor kernel from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled so that the calibration copy
+    of copy_bytes reads copy_bytes fetched and copy_bytes written."""
+    def copy_kib(path, counter):
+        vals = [v for k, v in _counter_rows(path, counter) if "copyBuffer" in k]
+        return max(vals)
+
+    scale_f = copy_bytes / (copy_kib(copy_fetch_csv, "FETCH_SIZE") * 1024.0)
+    scale_w = copy_bytes / (copy_kib(copy_write_csv, "WRITE_SIZE") * 1024.0)
+    res = {"source_sha256": _source_digest(), "copy_bytes": copy_bytes,
+           "scale_fetch": scale_f, "scale_write": scale_w, "kernels": {}}
+    for kern in FACTOR_KERNELS:
+        fv = [v for k, v in _counter_rows(fetch_csv, "FETCH_SIZE") if kern + "<double" in k]
+        wv = [v for k, v in _counter_rows(write_csv, "WRITE_SIZE") if kern + "<double" in k]
+        if not fv or not wv:
+            continue
+        res["kernels"][kern] = {
+            "launches": len(fv),
+            "fetch_bytes_per_launch": sum(fv) / len(fv) * 1024.0 * scale_f,
+            "write_bytes_per_launch": sum(wv) / len(wv) * 1024.0 * scale_w}
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the stored counter runs, or
+    None when there are none or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            res = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if res.get("source_sha256") != _source_digest() or kernel not in res.get("kernels", {}):
+        return None
+    k = res["kernels"][kernel]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,7 +182,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64 vs FP32+refinement comparison")
     ap.add_argument("--mixed-m", type=int, default=80, help="grid side of the mixed-precision workload")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES (byte-counter calibration)")
+    ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                        "COPY_WRITE_CSV", "COPY_BYTES"),
+                    help="only turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the stored "
+                         "per-launch HBM bytes of the factor kernels")
     args = ap.parse_args()
+    if args.write_traffic:
+        a = args.write_traffic
+        write_traffic(a[0], a[1], a[2], a[3], int(a[4]))
+        return
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -152,7 +241,6 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    assert an.status() == 0
 
     an.profile(True)
     torch.cuda.synchronize()
@@ -168,6 +256,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     an.profile(False)
+    assert an.status() == 0
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     # parts, timed separately with events (median of the same step count)
@@ -236,7 +325,10 @@ def main():
         "roofline": {"kernel": f"factor {dom} update (k_{dom})", "bound": "mfma",
                      "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
-                     "traffic": None},
+                     "traffic": stored_traffic(f"k_{dom}"),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
+                     "algorithmic_flops_per_launch": dom_flops_per_launch},
     }
     if not args.no_mixed:
         del an, rp
