@@ -19,6 +19,7 @@ struct sym_plan {
            off_wptr = 0, off_witems = 0, off_wmap = 0,
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
+           off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
            off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -38,7 +39,8 @@ struct sym_rhs_plan {
     std::vector<sym::SolveTask> tasks;  // forward tasks of the touched blocks, grouped by level
     std::vector<int32_t> bpos;       // permuted positions of b's nonzeros
     std::vector<int64_t> level_ptr;  // groups of `tasks` per nonempty level
-    size_t ws_bytes = 0, off_tasks = 0, off_bpos = 0;
+    std::vector<int32_t> pend;       // nb: chunks of `tasks` whose rows meet each block
+    size_t ws_bytes = 0, off_tasks = 0, off_bpos = 0, off_pend = 0;
     sym::DeviceRhs R;
     bool bound = false;
 };
@@ -78,6 +80,12 @@ void layout(sym_plan *h)
     h->off_acol = take(sizeof(int32_t) * P.acol.size());
     h->off_aval = take(sizeof(int64_t) * P.aval.size());
     h->off_red = take(sizeof(double) * 4);
+    h->off_ctp = take(sizeof(int64_t) * P.chunk_tptr.size());
+    h->off_ctg = take(sizeof(int32_t) * P.chunk_tgt.size());
+    h->off_fpend = take(sizeof(int32_t) * P.fwd_pend.size());
+    h->off_bpend = take(sizeof(int32_t) * P.bwd_pend.size());
+    h->off_bdf = take(sizeof(sym::SolveTask) * P.bwd_df.size());
+    h->off_sync = take(sizeof(int32_t) * (2 * (size_t)P.nb + 64));
     h->ws_bytes = o;
 }
 
@@ -170,6 +178,14 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.acol = (int32_t *)(base + h->off_acol);
     D.aval = (int64_t *)(base + h->off_aval);
     D.red = (double *)(base + h->off_red);
+    D.chunk_tptr = (int64_t *)(base + h->off_ctp);
+    D.chunk_tgt = (int32_t *)(base + h->off_ctg);
+    D.fwd_pend = (int32_t *)(base + h->off_fpend);
+    D.bwd_pend = (int32_t *)(base + h->off_bpend);
+    D.bwd_df = (sym::SolveTask *)(base + h->off_bdf);
+    D.pend = (int32_t *)(base + h->off_sync);
+    D.done = D.pend + P.nb;
+    D.ticket = D.done + P.nb;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
@@ -189,6 +205,13 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
         e = upload(D.fwd_tasks, P.fwd_tasks.data(), sizeof(sym::SolveTask) * P.fwd_tasks.size(), s);
     if (e == hipSuccess)
         e = upload(D.bwd_tasks, P.bwd_tasks.data(), sizeof(sym::SolveTask) * P.bwd_tasks.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.chunk_tptr, P.chunk_tptr.data(), sizeof(int64_t) * P.chunk_tptr.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.chunk_tgt, P.chunk_tgt.data(), sizeof(int32_t) * P.chunk_tgt.size(), s);
+    if (e == hipSuccess) e = upload(D.fwd_pend, P.fwd_pend.data(), sizeof(int32_t) * P.fwd_pend.size(), s);
+    if (e == hipSuccess) e = upload(D.bwd_pend, P.bwd_pend.data(), sizeof(int32_t) * P.bwd_pend.size(), s);
+    if (e == hipSuccess) e = upload(D.bwd_df, P.bwd_df.data(), sizeof(sym::SolveTask) * P.bwd_df.size(), s);
     if (e == hipSuccess) e = upload(D.arowptr, P.arowptr.data(), sizeof(int64_t) * P.arowptr.size(), s);
     if (e == hipSuccess) e = upload(D.acol, P.acol.data(), sizeof(int32_t) * P.acol.size(), s);
     if (e == hipSuccess) e = upload(D.aval, P.aval.data(), sizeof(int64_t) * P.aval.size(), s);
@@ -325,13 +348,22 @@ int sym_rhs_analyze(sym_handle h, int64_t nb, const int32_t *bi, sym_rhs *out)
             cur = P.blevel[b];
             const int32_t nch =
                 std::max(1, (P.blk[b].r - P.blk[b].w + sym::kSolveChunk - 1) / sym::kSolveChunk);
-            for (int32_t ch = 0; ch < nch; ++ch) r->tasks.push_back(sym::SolveTask{b, ch, bfirst[b], 0});
+            for (int32_t ch = 0; ch < nch; ++ch)
+                r->tasks.push_back(sym::SolveTask{b, ch, bfirst[b], P.fwd_first[b] + ch});
         }
         if (!r->tasks.empty()) r->level_ptr.push_back((int64_t)r->tasks.size());
+        // counters of the pruned sweep: only its own chunks contribute (the
+        // blocks they update hold ancestors of reached columns, so are
+        // touched themselves)
+        r->pend.assign((size_t)P.nb, 0);
+        for (const sym::SolveTask &t : r->tasks)
+            for (int64_t q = P.chunk_tptr[t.list]; q < P.chunk_tptr[t.list + 1]; ++q)
+                r->pend[P.chunk_tgt[q]]++;
         size_t o = 0;
         auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
         r->off_tasks = take(sizeof(sym::SolveTask) * r->tasks.size());
         r->off_bpos = take(sizeof(int32_t) * r->bpos.size());
+        r->off_pend = take(sizeof(int32_t) * r->pend.size());
         r->ws_bytes = std::max<size_t>(o, 256);
     } catch (const std::bad_alloc &) {
         delete r;
@@ -356,8 +388,11 @@ int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream)
     char *base = (char *)dev_ws;
     r->R.tasks = (sym::SolveTask *)(base + r->off_tasks);
     r->R.bpos = (int32_t *)(base + r->off_bpos);
+    r->R.pend = (int32_t *)(base + r->off_pend);
+    r->R.ntasks = (int64_t)r->tasks.size();
     hipError_t e = upload(r->R.tasks, r->tasks.data(), sizeof(sym::SolveTask) * r->tasks.size(), s);
     if (e == hipSuccess) e = upload(r->R.bpos, r->bpos.data(), sizeof(int32_t) * r->bpos.size(), s);
+    if (e == hipSuccess) e = upload(r->R.pend, r->pend.data(), sizeof(int32_t) * r->pend.size(), s);
     if (e != hipSuccess) return SYM_EHIP;
     r->bound = true;
     return SYM_OK;
@@ -371,8 +406,8 @@ int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double
     if (!h->bound || !h->factored || !r->bound) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     h->stream = s;
-    if (sym::launch_fwd_sparse(h->P, h->D, r->R, r->level_ptr, (int64_t)r->bpos.size(), bv_dev,
-                               h->D.vec, y_dev, s) != hipSuccess)
+    if (sym::launch_fwd_sparse(h->P, h->D, r->R, (int64_t)r->bpos.size(), bv_dev, h->D.vec, y_dev,
+                               s) != hipSuccess)
         return SYM_EHIP;
     return SYM_OK;
 }
@@ -382,9 +417,9 @@ int sym_status(sym_handle h, int64_t *info)
     if (!h || !info) return SYM_EINVAL;
     if (!h->bound || !h->factored) return SYM_ESTATE;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return SYM_EHIP;
-    int32_t w[2];
+    int32_t w[3];
     if (hipMemcpy(w, h->D.info, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return SYM_EHIP;
-    if (w[1] != INT32_MAX) return SYM_ESCHED;
+    if (w[1] != INT32_MAX || w[2] != 0) return SYM_ESCHED;
     *info = w[0] == INT32_MAX ? 0 : 1 + (int64_t)h->P.perm[w[0]];
     return SYM_OK;
 }

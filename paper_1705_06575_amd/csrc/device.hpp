@@ -36,12 +36,23 @@ struct DevicePlan {
     int32_t *acol = nullptr;
     int64_t *aval = nullptr;
     double *red = nullptr;          // reduction scalars of refinement
+    // dataflow sweeps
+    int64_t *chunk_tptr = nullptr;  // fwd tasks+1
+    int32_t *chunk_tgt = nullptr;   // target blocks of each chunk
+    int32_t *fwd_pend = nullptr;    // nb: initial counters of the forward sweep
+    int32_t *bwd_pend = nullptr;    // nb: initial counters of the backward sweep
+    SolveTask *bwd_df = nullptr;    // backward tasks in ticket order
+    int32_t *pend = nullptr;        // nb: live counters
+    int32_t *done = nullptr;        // nb: blocks whose backward solve is final
+    int32_t *ticket = nullptr;      // next task of a running sweep
 };
 
 // Reach-pruned forward sweep schedule, device view.
 struct DeviceRhs {
     SolveTask *tasks = nullptr;     // forward tasks of the touched blocks, grouped by level
     int32_t *bpos = nullptr;        // nb_rhs: permuted positions of b's nonzeros
+    int32_t *pend = nullptr;        // nb: initial counters of the pruned forward sweep
+    int64_t ntasks = 0;
 };
 
 // Optional per-launch event pairs for measurement: ev[2*i], ev[2*i+1]
@@ -65,8 +76,8 @@ hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double 
 hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *acc, double *out, hipStream_t s);
 hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s);
 hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs &R,
-                             const std::vector<int64_t> &level_ptr, int64_t nbeta,
-                             const double *bv, double *acc, double *out, hipStream_t s);
+                             int64_t nbeta, const double *bv, double *acc, double *out,
+                             hipStream_t s);
 
 // ---- iterative refinement (refine.hip)
 // r = b - A x (FP64); red[0] = max |r_i|, red[1] = max_i sum_j |A_ij|,

@@ -121,7 +121,12 @@ __global__ void k_scatter_a(const double *__restrict__ Ax, const int64_t *__rest
         Lx[amap[k]] = (T)Ax[k];
 }
 
-__global__ void k_info_reset(int32_t *info) { info[0] = INT32_MAX; info[1] = INT32_MAX; }
+__global__ void k_info_reset(int32_t *info)
+{
+    info[0] = INT32_MAX;
+    info[1] = INT32_MAX;
+    info[2] = 0;
+}
 
 // First position p in [lo, hi) with a[p] >= key (a sorted ascending); every
 // lane of the calling wavefront gets the result.  64-ary search: each round

@@ -96,11 +96,12 @@ struct Phase {
 constexpr int kTileRows = 64;   // T: rows per factor task tile
 constexpr int kSolveChunk = 256; // rows below the diagonal per forward-solve task
 
-struct SolveTask {      // 16 bytes: one chunk of one block in a forward sweep
+struct SolveTask {      // 16 bytes: one chunk of one block in a sweep
     int32_t J;
-    int32_t chunk;      // rows [w + chunk*kSolveChunk, ...) below the diagonal
+    int32_t chunk;      // rows [w + chunk*kSolveChunk, ...) below the diagonal;
+                        // -1: the block's diagonal solve (backward sweep)
     int32_t c0;         // first column of the block to solve (reach-pruned sweeps)
-    int32_t pad;
+    int32_t list;       // the chunk's target-block list (chunk_tptr), -1 if none
 };
 
 struct Plan {
@@ -149,6 +150,14 @@ struct Plan {
     std::vector<SolveTask> fwd_tasks;   // forward-sweep tasks grouped by level
     std::vector<int64_t> bwd_level_ptr; // nlevels+1 into bwd_tasks
     std::vector<SolveTask> bwd_tasks;   // backward off-diagonal chunks (blocks with rows below)
+    // dataflow form of the sweeps (one launch each): list q (= forward task
+    // q) holds the distinct blocks owning the rows of that chunk
+    std::vector<int32_t> fwd_first;     // nb: forward task of each block's chunk 0
+    std::vector<int64_t> chunk_tptr;    // fwd_tasks.size()+1
+    std::vector<int32_t> chunk_tgt;
+    std::vector<int32_t> fwd_pend;      // nb: forward chunks whose rows meet the block
+    std::vector<int32_t> bwd_pend;      // nb: off-diagonal chunks of the block
+    std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers, then diagonals
 
     // descendant pairs, grouped by target block
     std::vector<int64_t> dptr;      // nb+1

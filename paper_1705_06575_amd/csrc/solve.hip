@@ -10,22 +10,35 @@
 // elimination-tree paths; columns of a block that are not reached hold
 // exact zeros and contribute nothing).
 //
-// Forward, one launch per level, one workgroup per (block, chunk of 256 of
-// its rows below the diagonal): the block's diagonal triangle is staged in
-// LDS with coalesced loads; wavefront 0 solves it with the block's values
-// in registers (lane k owns y_k) -- every chunk of the block repeats this
-// small solve, which saves a second launch per level; chunk 0 stores the
-// solved values in the output vector; every thread then forms
-// sum_k L_ik y_k for one row (column-major reads contiguous across the
-// wavefront) and subtracts it from the accumulator entry of that row with
-// one atomic add.  Inputs are read from the accumulator and results written
-// to a separate output vector, so no task reads a value another task of the
-// same launch writes.
-// Backward (L^T x = y), two launches per level in reverse: chunks of each
-// block's rows below the diagonal subtract their share of L_offdiag^T x from
-// the block's entries (atomics), then one wavefront per block solves the
-// transposed diagonal triangle from LDS.
+// Each sweep is one persistent launch driven by data flow, not one launch
+// per level.  Workgroups take tasks by ticket (an atomic counter) in a
+// topological order; a task waits, with a bounded spin, until what it reads
+// is final, and signals what it produced:
+//   forward, task (block J, chunk of 256 rows below its diagonal): waits
+//   until every chunk whose rows meet J's columns has added its update into
+//   the accumulator (a per-block counter reaching zero); stages J's
+//   diagonal triangle in LDS and fetches its rows' L values before waiting;
+//   wavefront 0 solves the triangle (lane k owns y_k; every chunk of J
+//   repeats this small solve); chunk 0 stores y_J; every thread subtracts
+//   sum_k L_ik y_k from its row's accumulator entry (one atomic add); then
+//   it decrements the counter of every block its rows fall in.
+//   backward (L^T x = y), levels from the top: chunk tasks of J wait for the
+//   blocks owning their rows to be final, subtract their share of
+//   L_offdiag^T x from J's entries (atomics) and decrement J's counter;
+//   J's diagonal task waits for that counter, solves the transposed
+//   triangle and marks J final.
+// A task only waits for tasks with smaller tickets, which running
+// workgroups hold, so the launch always drains; a wait that exceeds its
+// bound (a corrupt plan) records an error and ends the launch.  Counters
+// are reset by a small kernel before each sweep.  Every value one task
+// hands to another within a launch (accumulator and solution entries,
+// counters, flags) is written and read with device-scope atomic operations,
+// which are coherent across the XCDs' separate L2 caches without cache-wide
+// write-back or invalidation; a producer waits for its own memory
+// operations to complete before it signals.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device.hpp"
 
@@ -89,6 +102,87 @@ __device__ __forceinline__ double row_dot(const T *__restrict__ L, int64_t ld, i
     return s;
 }
 
+// The same for exactly the 32 columns [c0, c0 + 32) (those past w read as
+// 0), all loads issued together.
+template <typename T>
+__device__ __forceinline__ double row_dot32(const T *__restrict__ L, int64_t ld, int64_t i,
+                                            const double *ys, int c0, int w)
+{
+    double lv[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const int k = min(c0 + j, w - 1);
+        lv[j] = (double)L[(int64_t)k * ld + i];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        if (c0 + j < w) s += lv[j] * ys[c0 + j];
+    return s;
+}
+
+// Forward substitution with the staged triangle D (stride LDT) by one
+// wavefront: lane i holds entry i of the right-hand side in v and
+// 1 / D[i][i] in rd, and returns y_i.  The columns are walked in groups of
+// 16 whose entries for this lane are read from LDS one group ahead, so each
+// step of the dependence chain is a cross-lane read, a product and a fused
+// multiply-add.
+__device__ __forceinline__ double tri_forward(const double *D, double v, double rd, int c0, int w)
+{
+    const int lane = threadIdx.x & 63;
+    double dn[16];
+    const int g0 = c0 & ~15;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dn[j] = D[(g0 + j) * LDT + lane];
+    for (int g = g0; g < w; g += 16) {
+        double dc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dc[j] = dn[j];
+        if (g + 16 < w) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) dn[j] = D[(g + 16 + j) * LDT + lane];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = g + j;
+            if (k >= c0 && k < w) {
+                const double xk = lane_value(v, k) * lane_value(rd, k);
+                v = lane == k ? xk : (lane > k ? v - dc[j] * xk : v);
+            }
+        }
+    }
+    return v;
+}
+
+// Backward substitution with the transposed triangle: lane i's entries of
+// row i of D are read one group of 16 columns ahead.
+__device__ __forceinline__ double tri_backward(const double *D, double v, double rd, int w)
+{
+    const int lane = threadIdx.x & 63;
+    double dn[16];
+    const int gl = (w - 1) & ~15;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dn[j] = D[lane * LDT + gl + j];
+    for (int g = gl; g >= 0; g -= 16) {
+        double dc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dc[j] = dn[j];
+        if (g >= 16) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) dn[j] = D[lane * LDT + g - 16 + j];
+        }
+#pragma unroll
+        for (int j = 15; j >= 0; --j) {
+            const int k = g + j;
+            if (k < w) {
+                const double xk = lane_value(v, k) * lane_value(rd, k);
+                v = lane == k ? xk : (lane < k ? v - dc[j] * xk : v);
+            }
+        }
+    }
+    return v;
+}
+
 __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict__ perm,
                          double *__restrict__ y, int32_t n)
 {
@@ -119,133 +213,243 @@ __global__ void k_place(const double *__restrict__ bv, const int32_t *__restrict
         y[bpos[k]] = bv[k];
 }
 
-// Forward sweep tasks of one level.  acc: right-hand side plus the updates
-// of earlier levels (read for the block's own columns, atomically updated
-// for the rows below); out: solved values of the block's columns.
+constexpr int kSpinLimit = 1 << 22;     // sleeps of ~0.2 us: about a second
+
+// Device-scope (coherent) load and store of a value handed between tasks.
+__device__ __forceinline__ double coherent_load(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every memory operation of the workgroup so far has completed (each
+// wavefront waits for its own, then the barrier), so a signal sent after
+// this is seen only after them.
+__device__ __forceinline__ void complete_then_sync()
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Spin until *p == 0; false, with the error word set, if the bound runs
+// out.
+__device__ __forceinline__ bool wait_zero(int32_t *p, int32_t *err)
+{
+    int it = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (++it > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+// Spin until *p != 0.
+__device__ __forceinline__ bool wait_set(int32_t *p, int32_t *err)
+{
+    int it = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if (++it > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+// Counters of a sweep from their initial values; done flags cleared.
+__global__ void k_sync_reset(int32_t *__restrict__ pend, const int32_t *__restrict__ init,
+                             int32_t *__restrict__ done, int32_t nb, int32_t *__restrict__ ticket)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+        pend[i] = init[i];
+        if (done) done[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ticket[0] = 0;
+}
+
+// Next task of a persistent launch for the whole workgroup, or -1 when the
+// list is exhausted or some wait of this launch ran out (then every
+// workgroup stops taking tasks, so the launch ends promptly).
+__device__ __forceinline__ int next_ticket(int32_t *ticket, int *s_t, int ntasks, int32_t *err)
+{
+    __syncthreads();                        // s_t of the previous task is no longer read
+    if (threadIdx.x == 0)
+        *s_t = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? ntasks
+                                                                                 : atomicAdd(ticket, 1);
+    __syncthreads();
+    const int t = *s_t;
+    return t < ntasks ? t : -1;
+}
+
+// Forward sweep, one persistent launch.  acc: right-hand side plus the
+// updates of finished chunks (read for a block's own columns once its
+// counter is zero, atomically updated for the rows below); out: solved
+// values of the blocks' columns.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_fwd(const SolveTask *__restrict__ tasks,
-                                            const BlockDesc *__restrict__ blk,
-                                            const int32_t *__restrict__ rows,
-                                            const T *__restrict__ Lx, double *__restrict__ acc,
-                                            double *__restrict__ out)
+__global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ tasks, int ntasks,
+                                               const int64_t *__restrict__ tptr,
+                                               const int32_t *__restrict__ tgt,
+                                               int32_t *__restrict__ pend, int32_t *ticket,
+                                               int32_t *err, const BlockDesc *__restrict__ blk,
+                                               const int32_t *__restrict__ rows,
+                                               const T *__restrict__ Lx, double *acc,
+                                               double *__restrict__ out)
 {
     __shared__ double D[64 * LDT];
     __shared__ double ys[64];
+    __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
-    const SolveTask tk = tasks[blockIdx.x];
-    const BlockDesc J = blk[tk.J];
-    const int c0 = tk.c0;
-    const T *L = Lx + J.valoff;
-    const int64_t ld = J.ld;
-    const int w = J.w;
-    stage_tri(D, L, ld, w, c0);
-    double v = 0.0;
-    if (tid < 64 && tid >= c0 && tid < w) v = acc[J.col0 + tid];
-    __syncthreads();
-    if (tid < 64) {
-        for (int k = c0; k < w; ++k) {
-            const double xk = lane_value(v, k) / D[k * LDT + k];
-            if (tid == k) v = xk;
-            else if (tid > k && tid < w) v -= D[k * LDT + tid] * xk;
+    if (tid == 0) s_abort = 0;
+    for (;;) {
+        const int t = next_ticket(ticket, &s_t, ntasks, err);
+        if (t < 0 || s_abort) break;
+        const SolveTask tk = tasks[t];
+        const BlockDesc J = blk[tk.J];
+        const int c0 = tk.c0;
+        const T *L = Lx + J.valoff;
+        const int64_t ld = J.ld;
+        const int w = J.w;
+        // what does not depend on other tasks: the triangle, this thread's
+        // row index and the row's first 32 values
+        stage_tri(D, L, ld, w, c0);
+        const int i = w + tk.chunk * NT + tid;
+        const bool has_row = i < J.r;
+        const int ic = has_row ? i : w - 1;
+        const int32_t row = rows[J.rowoff + ic];
+        double lv[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const int k = min(c0 + j, w - 1);
+            lv[j] = (double)L[(int64_t)k * ld + ic];
         }
-        ys[tid] = v;
-        if (tk.chunk == 0 && tid >= c0 && tid < w) out[J.col0 + tid] = v;
-    }
-    __syncthreads();
-    const int i = w + tk.chunk * NT + tid;
-    if (i < J.r) {
-        const int32_t row = rows[J.rowoff + i];
-        const double s = row_dot(L, ld, i, ys, c0, w);
-        atomicAdd(&acc[row], -s);
+        __syncthreads();                    // the staged triangle is readable
+        const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
+        if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
+        __syncthreads();
+        if (s_abort) break;
+        if (tid < 64) {
+            double v = (tid >= c0 && tid < w) ? coherent_load(&acc[J.col0 + tid]) : 0.0;
+            v = tri_forward(D, v, rd, c0, w);
+            ys[tid] = v;
+            if (tk.chunk == 0 && tid >= c0 && tid < w) out[J.col0 + tid] = v;
+        }
+        __syncthreads();
+        if (has_row) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 32; ++j)
+                if (c0 + j < w) s += lv[j] * ys[c0 + j];
+            if (c0 + 32 < w) s += row_dot32(L, ld, i, ys, c0 + 32, w);
+            atomicAdd(&acc[row], -s);
+        }
+        complete_then_sync();
+        for (int64_t q = tptr[tk.list] + tid; q < tptr[tk.list + 1]; q += NT)
+            __hip_atomic_fetch_add(&pend[tgt[q]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// Backward sweep, first half of a level: task (J, chunk) subtracts
-// sum_{i in chunk} L_ik x[row_i] from x[J's column k] for every k.  Wavefront v
-// takes columns k = v, v + 4, ..., lanes take rows (coalesced column-major
-// reads), a wavefront reduction per column, one atomic per column.  Tasks of
-// a level read only x of blocks of higher levels (already final) and write
-// only their own block's columns.
+// Backward sweep, one persistent launch over the tasks in ticket order
+// (levels from the top; per level the off-diagonal chunks, then the
+// diagonal solves).  x holds y on entry and the solution on exit.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_gather(const SolveTask *__restrict__ tasks,
-                                                   const BlockDesc *__restrict__ blk,
-                                                   const int32_t *__restrict__ rows,
-                                                   const T *__restrict__ Lx, double *__restrict__ x)
+__global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tasks, int ntasks,
+                                               const int64_t *__restrict__ tptr,
+                                               const int32_t *__restrict__ tgt,
+                                               int32_t *__restrict__ pend, int32_t *done,
+                                               int32_t *ticket, int32_t *err,
+                                               const BlockDesc *__restrict__ blk,
+                                               const int32_t *__restrict__ rows,
+                                               const T *__restrict__ Lx, double *x)
 {
+    __shared__ double D[64 * LDT];
+    __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const SolveTask tk = tasks[blockIdx.x];
-    const BlockDesc J = blk[tk.J];
-    const T *L = Lx + J.valoff;
-    const int64_t ld = J.ld;
-    const int w = J.w;
-    const int i0 = w + tk.chunk * NT;
-    const int i1 = min(J.r, i0 + NT);
-    const int32_t *rJ = rows + J.rowoff;
-    double part[16];
+    if (tid == 0) s_abort = 0;
+    for (;;) {
+        const int t = next_ticket(ticket, &s_t, ntasks, err);
+        if (t < 0 || s_abort) break;
+        const SolveTask tk = tasks[t];
+        const BlockDesc J = blk[tk.J];
+        const T *L = Lx + J.valoff;
+        const int64_t ld = J.ld;
+        const int w = J.w;
+        if (tk.chunk >= 0) {
+            // subtract sum_{i in chunk} L_ik x[row_i] from x[J's column k]:
+            // wavefront v takes columns v, v + 4, ..., lanes take rows
+            const int i0 = w + tk.chunk * NT;
+            const int i1 = min(J.r, i0 + NT);
+            const int32_t *rJ = rows + J.rowoff;
+            int32_t ri[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) part[q] = 0.0;
-    // the chunk's four rows per lane: indices, then x values, then L
-    int32_t ri[4];
-    double xr[4];
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + lane + 64 * u;
+                ri[u] = rJ[i < i1 ? i : i0];
+            }
+            // the blocks owning the chunk's rows must be final
+            bool ok = true;
+            for (int64_t q = tptr[tk.list] + tid; q < tptr[tk.list + 1]; q += NT)
+                ok = ok && wait_set(&done[tgt[q]], err);
+            if (!ok) s_abort = 1;
+            __syncthreads();
+            if (s_abort) break;
+            double xr[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = i0 + lane + 64 * u;
-        ri[u] = i < i1 ? rJ[i] : 0;
-    }
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + lane + 64 * u;
+                const double xv = coherent_load(&x[ri[u]]);
+                xr[u] = i < i1 ? xv : 0.0;
+            }
+            double part[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = i0 + lane + 64 * u;
-        const double xv = x[ri[u]];
-        xr[u] = i < i1 ? xv : 0.0;
-    }
+            for (int q = 0; q < 16; ++q) part[q] = 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = i0 + lane + 64 * u;
-        const int ic = i < i1 ? i : i0;
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + lane + 64 * u;
+                const int ic = i < i1 ? i : i0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k = wave + 4 * q;
-            const T val = L[(k < w ? (int64_t)k * ld : 0) + ic];
-            part[q] += (k < w ? (double)val : 0.0) * xr[u];
+                for (int q = 0; q < 16; ++q) {
+                    const int k = wave + 4 * q;
+                    const T val = L[(k < w ? (int64_t)k * ld : 0) + ic];
+                    part[q] += (k < w ? (double)val : 0.0) * xr[u];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = wave + 4 * q;
+                if (k < w) {
+                    double s2 = part[q];
+                    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+                    if (lane == 0) atomicAdd(&x[J.col0 + k], -s2);
+                }
+            }
+            complete_then_sync();
+            if (tid == 0)
+                __hip_atomic_fetch_add(&pend[tk.J], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            stage_tri(D, L, ld, w, 0);
+            __syncthreads();
+            const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
+            if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
+            __syncthreads();
+            if (s_abort) break;
+            if (tid < 64) {
+                double v = tid < w ? coherent_load(&x[J.col0 + tid]) : 0.0;
+                v = tri_backward(D, v, rd, w);
+                if (tid < w) coherent_store(&x[J.col0 + tid], v);
+            }
+            complete_then_sync();
+            if (tid == 0)
+                __hip_atomic_store(&done[tk.J], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int k = wave + 4 * q;
-        if (k < w) {
-            double s2 = part[q];
-            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
-            if (lane == 0) atomicAdd(&x[J.col0 + k], -s2);
-        }
-    }
-}
-
-// Backward sweep, second half of a level: each block solves its transposed
-// diagonal triangle, staged in LDS, with one wavefront (lane k owns x_k).
-template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_diag(const int32_t *__restrict__ blocks,
-                                                 const BlockDesc *__restrict__ blk,
-                                                 const T *__restrict__ Lx, double *__restrict__ x)
-{
-    __shared__ double D[64 * LDT];
-    const int tid = threadIdx.x;
-    const BlockDesc J = blk[blocks[blockIdx.x]];
-    const T *L = Lx + J.valoff;
-    const int64_t ld = J.ld;
-    const int w = J.w;
-    stage_tri(D, L, ld, w, 0);
-    double v = 0.0;
-    if (tid < w) v = x[J.col0 + tid];
-    __syncthreads();
-    if (tid < 64) {
-        for (int k = w - 1; k >= 0; --k) {
-            const double xk = lane_value(v, k) / D[k * LDT + k];
-            if (tid == k) v = xk;
-            else if (tid < k) v -= D[tid * LDT + k] * xk;
-        }
-        if (tid < w) x[J.col0 + tid] = v;
     }
 }
 
@@ -257,32 +461,34 @@ inline unsigned grid_for(int64_t count)
     return (unsigned)g;
 }
 
-template <typename T>
-hipError_t fwd_impl(const std::vector<int64_t> &level_ptr, const SolveTask *tasks,
-                    const DevicePlan &D, double *acc, double *out, hipStream_t s)
+// Workgroups of a persistent sweep: enough to fill the chip, at most one
+// per task.
+inline unsigned sweep_grid(int64_t ntasks)
 {
-    for (size_t l = 0; l + 1 < level_ptr.size(); ++l) {
-        const int64_t t0 = level_ptr[l], t1 = level_ptr[l + 1];
-        if (t1 > t0)
-            k_fwd<T><<<(unsigned)(t1 - t0), NT, 0, s>>>(tasks + t0, D.blk, D.rows, (const T *)D.Lx,
-                                                        acc, out);
-    }
+    return (unsigned)std::min<int64_t>(ntasks, 2048);
+}
+
+template <typename T>
+hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, int64_t ntasks,
+                    const int32_t *pend_init, double *acc, double *out, hipStream_t s)
+{
+    if (ntasks == 0) return hipGetLastError();
+    k_sync_reset<<<grid_for(P.nb), 256, 0, s>>>(D.pend, pend_init, nullptr, P.nb, D.ticket);
+    k_fwd_df<T><<<sweep_grid(ntasks), NT, 0, s>>>(tasks, (int)ntasks, D.chunk_tptr, D.chunk_tgt,
+                                                   D.pend, D.ticket, D.info + 2, D.blk, D.rows,
+                                                   (const T *)D.Lx, acc, out);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
 {
-    for (int32_t l = P.nlevels - 1; l >= 0; --l) {
-        const int64_t t0 = P.bwd_level_ptr[l], t1 = P.bwd_level_ptr[l + 1];
-        if (t1 > t0)
-            k_bwd_gather<T><<<(unsigned)(t1 - t0), NT, 0, s>>>(D.bwd_tasks + t0, D.blk, D.rows,
-                                                               (const T *)D.Lx, y);
-        const int32_t b0 = P.level_ptr[l], b1 = P.level_ptr[l + 1];
-        if (b1 > b0)
-            k_bwd_diag<T><<<(unsigned)(b1 - b0), NT, 0, s>>>(D.level_blocks + b0, D.blk,
-                                                             (const T *)D.Lx, y);
-    }
+    const int64_t ntasks = (int64_t)P.bwd_df.size();
+    if (ntasks == 0) return hipGetLastError();
+    k_sync_reset<<<grid_for(P.nb), 256, 0, s>>>(D.pend, D.bwd_pend, D.done, P.nb, D.ticket);
+    k_bwd_df<T><<<sweep_grid(ntasks), NT, 0, s>>>(D.bwd_df, (int)ntasks, D.chunk_tptr, D.chunk_tgt,
+                                                   D.pend, D.done, D.ticket, D.info + 2, D.blk,
+                                                   D.rows, (const T *)D.Lx, y);
     return hipGetLastError();
 }
 
@@ -304,8 +510,9 @@ hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double 
 
 hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *acc, double *out, hipStream_t s)
 {
-    return P.precision == 1 ? fwd_impl<float>(P.fwd_level_ptr, D.fwd_tasks, D, acc, out, s)
-                            : fwd_impl<double>(P.fwd_level_ptr, D.fwd_tasks, D, acc, out, s);
+    const int64_t nt = (int64_t)P.fwd_tasks.size();
+    return P.precision == 1 ? fwd_impl<float>(P, D, D.fwd_tasks, nt, D.fwd_pend, acc, out, s)
+                            : fwd_impl<double>(P, D, D.fwd_tasks, nt, D.fwd_pend, acc, out, s);
 }
 
 hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
@@ -314,13 +521,13 @@ hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t
 }
 
 hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs &R,
-                             const std::vector<int64_t> &level_ptr, int64_t nbeta,
-                             const double *bv, double *acc, double *out, hipStream_t s)
+                             int64_t nbeta, const double *bv, double *acc, double *out,
+                             hipStream_t s)
 {
     if (P.n > 0) k_zero2<<<grid_for(P.n), 256, 0, s>>>(acc, out, P.n);
     if (nbeta > 0) k_place<<<grid_for(nbeta), 256, 0, s>>>(bv, R.bpos, acc, nbeta);
-    return P.precision == 1 ? fwd_impl<float>(level_ptr, R.tasks, D, acc, out, s)
-                            : fwd_impl<double>(level_ptr, R.tasks, D, acc, out, s);
+    return P.precision == 1 ? fwd_impl<float>(P, D, R.tasks, R.ntasks, R.pend, acc, out, s)
+                            : fwd_impl<double>(P, D, R.tasks, R.ntasks, R.pend, acc, out, s);
 }
 
 }  // namespace sym

@@ -362,7 +362,7 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
             const int32_t b = P.level_blocks[q];
             const int32_t nch = std::max(1, (P.blk[b].r - P.blk[b].w + kSolveChunk - 1) / kSolveChunk);
-            for (int32_t c = 0; c < nch; ++c) P.fwd_tasks.push_back(SolveTask{b, c, 0, 0});
+            for (int32_t c = 0; c < nch; ++c) P.fwd_tasks.push_back(SolveTask{b, c, 0, -1});
         }
         P.fwd_level_ptr[l + 1] = (int64_t)P.fwd_tasks.size();
     }
@@ -372,9 +372,45 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
             const int32_t b = P.level_blocks[q];
             const int32_t nch = (P.blk[b].r - P.blk[b].w + kSolveChunk - 1) / kSolveChunk;
-            for (int32_t c = 0; c < nch; ++c) P.bwd_tasks.push_back(SolveTask{b, c, 0, 0});
+            for (int32_t c = 0; c < nch; ++c) P.bwd_tasks.push_back(SolveTask{b, c, 0, -1});
         }
         P.bwd_level_ptr[l + 1] = (int64_t)P.bwd_tasks.size();
+    }
+    // dataflow form: every chunk's distinct target blocks (its rows are
+    // increasing, so equal blocks are adjacent), the number of chunks that
+    // update each block, and the backward order
+    P.fwd_first.assign((size_t)nb, 0);
+    P.chunk_tptr.assign(1, 0);
+    P.chunk_tgt.clear();
+    P.fwd_pend.assign((size_t)nb, 0);
+    for (size_t q = 0; q < P.fwd_tasks.size(); ++q) {
+        SolveTask &t = P.fwd_tasks[q];
+        const BlockDesc &d = P.blk[t.J];
+        if (t.chunk == 0) P.fwd_first[t.J] = (int32_t)q;
+        t.list = (int32_t)q;
+        const int32_t i0 = d.w + t.chunk * kSolveChunk, i1 = std::min(d.r, i0 + kSolveChunk);
+        int32_t last = -1;
+        for (int32_t i = i0; i < i1; ++i) {
+            const int32_t b2 = P.col2blk[P.dsrows[d.rowoff + i]];
+            if (b2 != last) {
+                P.chunk_tgt.push_back(b2);
+                P.fwd_pend[b2]++;
+                last = b2;
+            }
+        }
+        P.chunk_tptr.push_back((int64_t)P.chunk_tgt.size());
+    }
+    P.bwd_pend.assign((size_t)nb, 0);
+    P.bwd_df.clear();
+    for (int32_t l = P.nlevels - 1; l >= 0; --l) {
+        for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+            const int32_t b = P.level_blocks[q];
+            const int32_t nch = (P.blk[b].r - P.blk[b].w + kSolveChunk - 1) / kSolveChunk;
+            P.bwd_pend[b] = nch;
+            for (int32_t c = 0; c < nch; ++c) P.bwd_df.push_back(SolveTask{b, c, 0, P.fwd_first[b] + c});
+        }
+        for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q)
+            P.bwd_df.push_back(SolveTask{P.level_blocks[q], -1, 0, -1});
     }
 
     // ------------------------------------------ descendant pairs (prune set)
