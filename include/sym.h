@@ -145,6 +145,20 @@ int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *
                int32_t maxit, void *stream, int32_t *iters, double *eta);
 
 /*
+ * The same solve with the refinement accelerated by conjugate gradients:
+ * preconditioned CG in FP64 on A x = b, the preconditioner being the
+ * current factor (M = P^T L^-T L^-1 P, symmetric positive definite like A,
+ * so CG applies), started from x0 = M b.  Every step computes the true FP64
+ * residual r = b - A x (used in place of the recurrence) and its eta as
+ * sym_refine; the stopping rule and outputs are those of sym_refine, with
+ * *iters counting applications of M after the first.  Dot products are
+ * reduced in a fixed order (bitwise reproducible).  Synchronizes the
+ * stream three times per step.  Errors as sym_refine.
+ */
+int sym_refine_pcg(sym_handle h, const double *Ax_dev, const double *b_dev, double *x_dev,
+                   double tol, int32_t maxit, void *stream, int32_t *iters, double *eta);
+
+/*
  * Reach-set inspector for one right-hand-side pattern, host only (Section
  * 1.1, Gilbert-Peierls: Reach_L(beta) is the set of columns reachable in the
  * dependence graph of L from beta = {i : b_i != 0}; numerical cancellation

@@ -53,7 +53,8 @@ EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_
            "sym_solve", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
            "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
            "sym_export_factor", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
-           "sym_profile", "sym_profile_read", "sym_refine", "sym_destroy", "sym_rhs_destroy"]
+           "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
+           "sym_rhs_destroy"]
 
 _lib = None
 
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     L.sym_stat.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.sym_refine.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp,
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    L.sym_refine_pcg.argtypes = L.sym_refine.argtypes
     L.sym_profile.argtypes = [vp, ctypes.c_int]
     L.sym_profile_read.argtypes = [vp, vp, vp, vp]
     L.sym_destroy.restype = None
@@ -243,14 +245,19 @@ class Analysis:
         _check("sym_solve", self._lib.sym_solve(self._h, _dev_ptr(bx, "torch.float64", self.n), _stream()))
         return bx
 
-    def refine(self, Ax, b, tol=1e-12, maxit=20, out=None):
+    def refine(self, Ax, b, tol=1e-12, maxit=20, out=None, method="ir"):
         """x solving A x = b by the current factor plus FP64 iterative
-        refinement on the device.  Returns (x, iterations, eta_inf)."""
+        refinement on the device: method "ir" (classical, sym_refine) or
+        "pcg" (conjugate-gradient accelerated, sym_refine_pcg).  Returns
+        (x, iterations, eta_inf)."""
         import torch
+        if method not in ("ir", "pcg"):
+            raise ValueError(f"method {method!r}: 'ir' or 'pcg'")
+        name = "sym_refine" if method == "ir" else "sym_refine_pcg"
         x = out if out is not None else torch.empty_like(b)
         it = ctypes.c_int32()
         eta = ctypes.c_double()
-        _check("sym_refine", self._lib.sym_refine(
+        _check(name, getattr(self._lib, name)(
             self._h, _dev_ptr(Ax, "torch.float64", self.nnzA), _dev_ptr(b, "torch.float64", self.n),
             _dev_ptr(x, "torch.float64", self.n), float(tol), int(maxit), _stream(),
             ctypes.byref(it), ctypes.byref(eta)))

@@ -20,6 +20,7 @@ struct sym_plan {
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
+           off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0,
            off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -86,6 +87,10 @@ void layout(sym_plan *h)
     h->off_bpend = take(sizeof(int32_t) * P.bwd_pend.size());
     h->off_bdf = take(sizeof(sym::SolveTask) * P.bwd_df.size());
     h->off_sync = take(sizeof(int32_t) * (2 * (size_t)P.nb + 64));
+    h->off_vec4 = take(sizeof(double) * (size_t)P.n);
+    h->off_vec5 = take(sizeof(double) * (size_t)P.n);
+    h->off_vec6 = take(sizeof(double) * (size_t)P.n);
+    h->off_part = take(sizeof(double) * (sym::kDotParts + 8));
     h->ws_bytes = o;
 }
 
@@ -186,6 +191,10 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.pend = (int32_t *)(base + h->off_sync);
     D.done = D.pend + P.nb;
     D.ticket = D.done + P.nb;
+    D.vec4 = (double *)(base + h->off_vec4);
+    D.vec5 = (double *)(base + h->off_vec5);
+    D.vec6 = (double *)(base + h->off_vec6);
+    D.part = (double *)(base + h->off_part);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
@@ -304,6 +313,70 @@ int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *
         rc = sym_solve(h, D.vec3, stream);           // correction, in place
         if (rc != SYM_OK) return rc;
         if (sym::launch_axpy(P, x_dev, D.vec3, s) != hipSuccess) return SYM_EHIP;
+        ++it;
+    }
+    if (iters) *iters = it;
+    if (eta) *eta = e;
+    return SYM_OK;
+}
+
+int sym_refine_pcg(sym_handle h, const double *Ax_dev, const double *b_dev, double *x_dev,
+                   double tol, int32_t maxit, void *stream, int32_t *iters, double *eta)
+{
+    if (!h || ((!Ax_dev || !b_dev || !x_dev) && h->P.n) || maxit < 0 || !(tol >= 0.0)) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    const sym::Plan &P = h->P;
+    const sym::DevicePlan &D = h->D;
+    const size_t bytes = sizeof(double) * (size_t)P.n;
+    if (P.n == 0) {
+        if (iters) *iters = 0;
+        if (eta) *eta = 0.0;
+        return SYM_OK;
+    }
+    double *r = D.vec3, *p = D.vec4, *q = D.vec5, *z = D.vec6;
+    double *scal = D.part + sym::kDotParts;     // device slots of the dot products
+    auto fetch = [&](const double *dev, double *host, size_t count) {
+        if (hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+        return hipStreamSynchronize(s) == hipSuccess;
+    };
+    // x0 = M b
+    if (hipMemcpyAsync(x_dev, b_dev, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SYM_EHIP;
+    int rc = sym_solve(h, x_dev, stream);
+    if (rc != SYM_OK) return rc;
+    double anorm = 0.0, e = 0.0, rho = 0.0;
+    int32_t it = 0;
+    for (;;) {
+        // true residual and its backward error
+        if (sym::launch_residual(P, D, Ax_dev, b_dev, x_dev, r, it == 0, s) != hipSuccess) return SYM_EHIP;
+        double cur[4];
+        if (!fetch(D.red, cur, 4)) return SYM_EHIP;
+        if (it == 0) anorm = cur[1];
+        const double den = anorm * cur[2] + cur[3];
+        e = den > 0.0 ? cur[0] / den : cur[0];
+        if (!(e > tol) || it >= maxit) break;      // also stops on NaN
+        // z = M r, rho' = r . z, p = z + (rho' / rho) p
+        if (hipMemcpyAsync(z, r, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SYM_EHIP;
+        rc = sym_solve(h, z, stream);
+        if (rc != SYM_OK) return rc;
+        if (sym::launch_dot(P, D, r, z, scal, s) != hipSuccess) return SYM_EHIP;
+        double rho_new;
+        if (!fetch(scal, &rho_new, 1)) return SYM_EHIP;
+        if (it == 0) {
+            if (hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SYM_EHIP;
+        } else if (sym::launch_xpby(P, p, z, rho_new / rho, s) != hipSuccess) {
+            return SYM_EHIP;
+        }
+        rho = rho_new;
+        // x += (rho / p.Ap) p
+        if (sym::launch_spmv(P, D, Ax_dev, p, q, s) != hipSuccess) return SYM_EHIP;
+        if (sym::launch_dot(P, D, p, q, scal + 1, s) != hipSuccess) return SYM_EHIP;
+        double pq;
+        if (!fetch(scal + 1, &pq, 1)) return SYM_EHIP;
+        if (!(pq > 0.0)) break;                        // breakdown (not SPD, or converged to 0)
+        if (sym::launch_axpy_s(P, x_dev, rho / pq, p, s) != hipSuccess) return SYM_EHIP;
         ++it;
     }
     if (iters) *iters = it;

@@ -36,6 +36,10 @@ struct DevicePlan {
     int32_t *acol = nullptr;
     int64_t *aval = nullptr;
     double *red = nullptr;          // reduction scalars of refinement
+    double *vec4 = nullptr;         // n scratch: conjugate-gradient direction p
+    double *vec5 = nullptr;         // n scratch: A p
+    double *vec6 = nullptr;         // n scratch: preconditioned residual z
+    double *part = nullptr;         // kDotParts partial sums of a dot product
     // dataflow sweeps
     int64_t *chunk_tptr = nullptr;  // fwd tasks+1
     int32_t *chunk_tgt = nullptr;   // target blocks of each chunk
@@ -86,5 +90,16 @@ hipError_t launch_residual(const Plan &P, const DevicePlan &D, const double *Ax,
                            const double *x, double *r, bool with_anorm, hipStream_t s);
 // x += d
 hipError_t launch_axpy(const Plan &P, double *x, const double *d, hipStream_t s);
+// q = A p (FP64, full symmetric rows of A)
+hipError_t launch_spmv(const Plan &P, const DevicePlan &D, const double *Ax, const double *p,
+                       double *q, hipStream_t s);
+// *out (device) = u . v, reduced in a fixed order
+constexpr int kDotParts = 1024;
+hipError_t launch_dot(const Plan &P, const DevicePlan &D, const double *u, const double *v,
+                      double *out, hipStream_t s);
+// y += a x
+hipError_t launch_axpy_s(const Plan &P, double *y, double a, const double *x, hipStream_t s);
+// p = z + b p
+hipError_t launch_xpby(const Plan &P, double *p, const double *z, double b, hipStream_t s);
 
 }  // namespace sym

@@ -1,7 +1,9 @@
 // refine.hip -- FP64 residual and update kernels of mixed-precision
 // iterative refinement: x0 = solve(b) with the (FP32 or FP64) factor, then
 // r = b - A x in FP64, eta_inf = |r|_inf / (|A|_inf |x|_inf + |b|_inf), and
-// x += solve(r) until eta_inf reaches the tolerance.
+// x += solve(r) until eta_inf reaches the tolerance; plus the matrix-vector
+// product, dot products and vector updates of the conjugate-gradient form
+// of the refinement.  Dot products are reduced in two fixed-order passes.
 //
 // The residual runs over the full symmetric pattern of A stored by rows
 // (built by the analysis from the lower-triangle input), one thread per row,
@@ -75,6 +77,62 @@ __global__ void k_axpy(double *__restrict__ x, const double *__restrict__ d, int
         x[i] += d[i];
 }
 
+// q = A p over the full symmetric rows, one thread per row.
+__global__ __launch_bounds__(256) void k_spmv(const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col,
+                                              const int64_t *__restrict__ val,
+                                              const double *__restrict__ Ax,
+                                              const double *__restrict__ p,
+                                              double *__restrict__ q, int32_t n)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) s += Ax[val[k]] * p[col[k]];
+        q[i] = s;
+    }
+}
+
+// Dot product, first pass: workgroup g sums entries g, g + G, ... (a fixed
+// order per thread, then a fixed tree) into part[g].
+__global__ __launch_bounds__(256) void k_dot_part(const double *__restrict__ u,
+                                                  const double *__restrict__ v,
+                                                  double *__restrict__ part, int32_t n)
+{
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        s += u[i] * v[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Second pass: one workgroup sums the kDotParts partials in a fixed tree.
+__global__ __launch_bounds__(256) void k_dot_final(const double *__restrict__ part,
+                                                   double *__restrict__ out)
+{
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < kDotParts; i += 256) s += part[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void k_axpy_s(double *__restrict__ y, double a, const double *__restrict__ x, int32_t n)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+__global__ void k_xpby(double *__restrict__ p, const double *__restrict__ z, double b, int32_t n)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = z[i] + b * p[i];
+}
+
 inline unsigned grid_for(int64_t count)
 {
     int64_t g = (count + 255) / 256;
@@ -98,6 +156,33 @@ hipError_t launch_residual(const Plan &P, const DevicePlan &D, const double *Ax,
 hipError_t launch_axpy(const Plan &P, double *x, const double *d, hipStream_t s)
 {
     if (P.n > 0) k_axpy<<<grid_for(P.n), 256, 0, s>>>(x, d, P.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(const Plan &P, const DevicePlan &D, const double *Ax, const double *p,
+                       double *q, hipStream_t s)
+{
+    if (P.n > 0) k_spmv<<<grid_for(P.n), 256, 0, s>>>(D.arowptr, D.acol, D.aval, Ax, p, q, P.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const Plan &P, const DevicePlan &D, const double *u, const double *v,
+                      double *out, hipStream_t s)
+{
+    k_dot_part<<<kDotParts, 256, 0, s>>>(u, v, D.part, P.n);
+    k_dot_final<<<1, 256, 0, s>>>(D.part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_s(const Plan &P, double *y, double a, const double *x, hipStream_t s)
+{
+    if (P.n > 0) k_axpy_s<<<grid_for(P.n), 256, 0, s>>>(y, a, x, P.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpby(const Plan &P, double *p, const double *z, double b, hipStream_t s)
+{
+    if (P.n > 0) k_xpby<<<grid_for(P.n), 256, 0, s>>>(p, z, b, P.n);
     return hipGetLastError();
 }
 

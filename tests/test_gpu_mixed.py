@@ -68,10 +68,12 @@ def test_fp32_factor_matches_oracle(S, orc, torch_cuda):
             assert e <= 1e-5
 
 
+@pytest.mark.parametrize("method", ["ir", "pcg"])
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_refinement_reaches_1e12(S, orc, torch_cuda, precision):
+def test_refinement_reaches_1e12(S, orc, torch_cuda, precision, method):
     """3-D 27-point weighted Laplacian (the mixed-precision workload's
-    recipe, 20^3): FP32 or FP64 factor, FP64 refinement to eta <= 1e-12."""
+    recipe, 20^3): FP32 or FP64 factor, FP64 refinement (classical or
+    conjugate-gradient accelerated) to eta <= 1e-12."""
     torch = torch_cuda
     w = W.config3(20)
     an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", precision=precision)
@@ -79,13 +81,13 @@ def test_refinement_reaches_1e12(S, orc, torch_cuda, precision):
     an.factor(Ax)
     assert an.status() == 0
     b = W.dense_rhs(w.n, np.random.default_rng(7))
-    x, iters, eta = an.refine(Ax, torch.from_numpy(b).cuda(), tol=1e-12, maxit=30)
+    x, iters, eta = an.refine(Ax, torch.from_numpy(b).cuda(), tol=1e-12, maxit=30, method=method)
     x = x.cpu().numpy()
     eta_orc = orc.eta_inf(w.n, w.Ap, w.Ai, w.Ax, x, b)
     f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
     x_ref = orc.solve(w.n, w.perm, f["Lp"], f["Li"], f["Lx"], b)
     e = _rel(x, x_ref)
-    _say(f"case refine {precision} {w.name}: iters {iters} eta {eta:.2e} (oracle {eta_orc:.2e}) "
+    _say(f"case refine {method} {precision} {w.name}: iters {iters} eta {eta:.2e} (oracle {eta_orc:.2e}) "
          f"x rel diff {e:.2e}")
     assert eta <= 1e-12 and eta_orc <= 1e-12
     # the two residuals differ by summation order: at most rounding noise,
@@ -98,6 +100,23 @@ def test_refinement_reaches_1e12(S, orc, torch_cuda, precision):
     # solution error of a backward-stable result: at most kappa * eta; the
     # recipe's kappa (row-sum scaled) is ~1e6, so 1e6 * 1e-12 bounds it
     assert e <= 1e-5
+
+
+def test_pcg_needs_fewer_corrections_than_ir(S, torch_cuda):
+    """On the ill-conditioned recipe the conjugate-gradient form reaches
+    1e-12 with fewer applications of the FP32 factor than classical
+    refinement (both from the same factor and right-hand side)."""
+    torch = torch_cuda
+    w = W.config3(24)
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", precision="f32")
+    Ax = torch.from_numpy(w.Ax).cuda()
+    an.factor(Ax)
+    b = torch.from_numpy(W.dense_rhs(w.n, np.random.default_rng(9))).cuda()
+    _, it_ir, eta_ir = an.refine(Ax, b, tol=1e-12, maxit=60, method="ir")
+    _, it_cg, eta_cg = an.refine(Ax, b, tol=1e-12, maxit=60, method="pcg")
+    _say(f"case ir vs pcg: ir {it_ir} ({eta_ir:.1e}), pcg {it_cg} ({eta_cg:.1e})")
+    assert eta_ir <= 1e-12 and eta_cg <= 1e-12
+    assert it_cg <= it_ir
 
 
 def test_refinement_reports_stagnation(S, torch_cuda):
