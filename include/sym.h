@@ -245,6 +245,42 @@ int sym_stat(sym_handle h, int what, double *value);
 int sym_profile(sym_handle h, int enable);
 int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algorithmic_flops);
 
+/*
+ * Batches: m value sets on the pattern of one analysis (Section 1.2: the
+ * pattern is fixed while the values change), factored and solved together,
+ * one launch per step of the schedule for all m (the instances occupy the
+ * launches' second grid dimension).  The batch uses the analysis's bound
+ * plan (h must stay bound and alive) and owns, in its own caller-allocated
+ * workspace, m sets of panels, scratch vectors, status words and sweep
+ * counters.  Layouts: Ax_dev is m x nnz(A) (instance-major, each in
+ * sym_analyze's order); right-hand sides and solutions are m x n, original
+ * ordering.  No batch call except sym_batch_eta and sym_batch_status
+ * synchronizes; none allocates or records a memset, so a sequence of them
+ * can be captured into a HIP graph and replayed.
+ *
+ * sym_batch_create: 1 <= m <= 65535.  sym_batch_bind: h must be bound
+ * (SYM_ESTATE otherwise); alignment and size rules as sym_bind.
+ * sym_batch_factor: factor all m value sets.  sym_batch_solve: in place,
+ * A_i x_i = b_i for every instance.  sym_batch_refine: x_i = solve(b_i)
+ * followed by exactly `steps` FP64 refinement steps r = b - A x, x +=
+ * solve(r) (no stopping test, so no host synchronization).
+ * sym_batch_eta: eta_host[i] = the normwise backward error of x_i (as
+ * sym_refine).  sym_batch_status: info_host[i] as sym_status for instance
+ * i; returns SYM_ESCHED if any instance's device scheduler gave up.
+ */
+typedef struct sym_batch *sym_batch_t;
+int sym_batch_create(sym_handle h, int32_t m, sym_batch_t *out);
+int sym_batch_workspace(sym_batch_t b, size_t *bytes);
+int sym_batch_bind(sym_batch_t b, void *dev_ws, size_t bytes, void *stream);
+int sym_batch_factor(sym_batch_t b, const double *Ax_dev, void *stream);
+int sym_batch_solve(sym_batch_t b, double *bx_dev, void *stream);
+int sym_batch_refine(sym_batch_t b, const double *Ax_dev, const double *b_dev, double *x_dev,
+                     int32_t steps, void *stream);
+int sym_batch_eta(sym_batch_t b, const double *Ax_dev, const double *b_dev, const double *x_dev,
+                  double *eta_host, void *stream);
+int sym_batch_status(sym_batch_t b, int64_t *info_host);
+void sym_batch_destroy(sym_batch_t b);
+
 void sym_destroy(sym_handle h);
 void sym_rhs_destroy(sym_rhs r);
 

@@ -54,7 +54,9 @@ EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_
            "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
            "sym_export_factor", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
            "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
-           "sym_rhs_destroy"]
+           "sym_rhs_destroy", "sym_batch_create", "sym_batch_workspace", "sym_batch_bind",
+           "sym_batch_factor", "sym_batch_solve", "sym_batch_refine", "sym_batch_eta",
+           "sym_batch_status", "sym_batch_destroy"]
 
 _lib = None
 
@@ -96,9 +98,20 @@ def load_library(path: str = LIB_PATH):
     L.sym_destroy.argtypes = [vp]
     L.sym_rhs_destroy.restype = None
     L.sym_rhs_destroy.argtypes = [vp]
+    L.sym_batch_create.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.sym_batch_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    L.sym_batch_bind.argtypes = [vp, vp, sz, vp]
+    L.sym_batch_factor.argtypes = [vp, vp, vp]
+    L.sym_batch_solve.argtypes = [vp, vp, vp]
+    L.sym_batch_refine.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp]
+    L.sym_batch_eta.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.sym_batch_status.argtypes = [vp, vp]
+    L.sym_batch_destroy.restype = None
+    L.sym_batch_destroy.argtypes = [vp]
+    no_ret = ("sym_opts_default", "sym_destroy", "sym_rhs_destroy", "sym_batch_destroy")
     for name in EXPORTS:
         f = getattr(L, name)
-        if f.restype is not None and name not in ("sym_opts_default", "sym_destroy", "sym_rhs_destroy"):
+        if f.restype is not None and name not in no_ret:
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -361,6 +374,80 @@ class RhsPlan:
         if getattr(self, "_r", None) is not None and self._r.value:
             self._lib.sym_rhs_destroy(self._r)
             self._r = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """m value sets on the pattern of one bound Analysis, factored and
+    solved together (one launch per schedule step for all of them).
+    Values: float64 tensors of shape (m, nnz(A)); right-hand sides and
+    solutions (m, n).  Every call is asynchronous and allocation-free
+    except eta() and status(), so a sequence can be captured in a graph."""
+
+    def __init__(self, an: Analysis, m: int, device=None):
+        import torch
+        if an._ws is None:
+            an.bind(device)
+        self._an = an
+        self._lib = an._lib
+        self.m = int(m)
+        b = ctypes.c_void_p()
+        _check("sym_batch_create", self._lib.sym_batch_create(an._h, self.m, ctypes.byref(b)))
+        self._b = b
+        nb = ctypes.c_size_t()
+        _check("sym_batch_workspace", self._lib.sym_batch_workspace(b, ctypes.byref(nb)))
+        self._ws = torch.empty(nb.value + 256, dtype=torch.uint8,
+                               device=device if device is not None else an._ws.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check("sym_batch_bind", self._lib.sym_batch_bind(
+            b, ctypes.c_void_p(aligned), ctypes.c_size_t(nb.value + 256 - (aligned - base)),
+            _stream()))
+
+    def factor(self, Ax):
+        _check("sym_batch_factor", self._lib.sym_batch_factor(
+            self._b, _dev_ptr(Ax, "torch.float64", self.m * self._an.nnzA), _stream()))
+        return self
+
+    def solve_(self, B):
+        """In place: row i of B becomes A_i^-1 B_i."""
+        _check("sym_batch_solve", self._lib.sym_batch_solve(
+            self._b, _dev_ptr(B, "torch.float64", self.m * self._an.n), _stream()))
+        return B
+
+    def refine(self, Ax, B, X, steps: int):
+        """X_i = solve(B_i) plus `steps` FP64 refinement steps (no host sync)."""
+        n = self.m * self._an.n
+        _check("sym_batch_refine", self._lib.sym_batch_refine(
+            self._b, _dev_ptr(Ax, "torch.float64", self.m * self._an.nnzA),
+            _dev_ptr(B, "torch.float64", n), _dev_ptr(X, "torch.float64", n), int(steps),
+            _stream()))
+        return X
+
+    def eta(self, Ax, B, X) -> np.ndarray:
+        """Normwise backward error of every instance (synchronizes)."""
+        n = self.m * self._an.n
+        out = np.zeros(self.m)
+        _check("sym_batch_eta", self._lib.sym_batch_eta(
+            self._b, _dev_ptr(Ax, "torch.float64", self.m * self._an.nnzA),
+            _dev_ptr(B, "torch.float64", n), _dev_ptr(X, "torch.float64", n), _ptr(out),
+            _stream()))
+        return out
+
+    def status(self) -> np.ndarray:
+        out = np.zeros(self.m, dtype=np.int64)
+        _check("sym_batch_status", self._lib.sym_batch_status(self._b, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._lib.sym_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -312,7 +312,7 @@ int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *
         if (!(e > tol) || it >= maxit) break;      // also stops on NaN
         rc = sym_solve(h, D.vec3, stream);           // correction, in place
         if (rc != SYM_OK) return rc;
-        if (sym::launch_axpy(P, x_dev, D.vec3, s) != hipSuccess) return SYM_EHIP;
+        if (sym::launch_axpy(P, D, x_dev, D.vec3, s) != hipSuccess) return SYM_EHIP;
         ++it;
     }
     if (iters) *iters = it;
@@ -670,5 +670,169 @@ int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algori
 
 void sym_destroy(sym_handle h) { delete h; }
 void sym_rhs_destroy(sym_rhs r) { delete r; }
+
+
+// ------------------------------------------------------------------ batches
+
+struct sym_batch {
+    sym_plan *h = nullptr;
+    int32_t m = 0;
+    size_t ws_bytes = 0, off_Lx = 0, off_vec = 0, off_vec2 = 0, off_vec3 = 0, off_info = 0,
+           off_red = 0, off_sync = 0;
+    sym::DevicePlan D;              // the analysis's plan arrays, the batch's own buffers
+    bool bound = false, factored = false;
+    hipStream_t stream = nullptr;
+};
+
+int sym_batch_create(sym_handle h, int32_t m, sym_batch_t *out)
+{
+    if (!h || !out || m < 1 || m > 65535) return SYM_EINVAL;
+    *out = nullptr;
+    sym_batch *b = new (std::nothrow) sym_batch();
+    if (!b) return SYM_ENOMEM;
+    b->h = h;
+    b->m = m;
+    const sym::Plan &P = h->P;
+    const size_t M = (size_t)m;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    b->off_Lx = take(M * (size_t)P.panel_entries * elem_size(P));
+    b->off_vec = take(M * sizeof(double) * (size_t)P.n);
+    b->off_vec2 = take(M * sizeof(double) * (size_t)P.n);
+    b->off_vec3 = take(M * sizeof(double) * (size_t)P.n);
+    b->off_info = take(M * sizeof(int32_t) * 4);
+    b->off_red = take(M * sizeof(double) * 4);
+    b->off_sync = take(M * sizeof(int32_t) * (2 * (size_t)P.nb + 16));
+    b->ws_bytes = std::max<size_t>(o, 256);
+    *out = b;
+    return SYM_OK;
+}
+
+int sym_batch_workspace(sym_batch_t b, size_t *bytes)
+{
+    if (!b || !bytes) return SYM_EINVAL;
+    *bytes = b->ws_bytes;
+    return SYM_OK;
+}
+
+int sym_batch_bind(sym_batch_t b, void *dev_ws, size_t bytes, void *stream)
+{
+    if (!b || !dev_ws) return SYM_EINVAL;
+    if (!b->h->bound) return SYM_ESTATE;
+    if (bytes < b->ws_bytes || ((uintptr_t)dev_ws & 255)) return SYM_EWORKSPACE;
+    const sym::Plan &P = b->h->P;
+    char *base = (char *)dev_ws;
+    sym::DevicePlan D = b->h->D;
+    D.m = b->m;
+    D.Lx = base + b->off_Lx;
+    D.vec = (double *)(base + b->off_vec);
+    D.vec2 = (double *)(base + b->off_vec2);
+    D.vec3 = (double *)(base + b->off_vec3);
+    D.info = (int32_t *)(base + b->off_info);
+    D.red = (double *)(base + b->off_red);
+    D.pend = (int32_t *)(base + b->off_sync);
+    D.done = D.pend + (size_t)b->m * P.nb;
+    D.ticket = D.done + (size_t)b->m * P.nb;
+    // single-instance scratch of the analysis is not used by batches
+    D.vec4 = D.vec5 = D.vec6 = D.part = nullptr;
+    b->D = D;
+    b->stream = (hipStream_t)stream;
+    b->bound = true;
+    b->factored = false;
+    return SYM_OK;
+}
+
+int sym_batch_factor(sym_batch_t b, const double *Ax_dev, void *stream)
+{
+    if (!b || (!Ax_dev && b->h->P.nnzA)) return SYM_EINVAL;
+    if (!b->bound || !b->h->bound) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    b->stream = s;
+    if (sym::launch_factor(b->h->P, b->D, Ax_dev, s, nullptr) != hipSuccess) return SYM_EHIP;
+    b->factored = true;
+    return SYM_OK;
+}
+
+int sym_batch_solve(sym_batch_t b, double *bx_dev, void *stream)
+{
+    if (!b || (!bx_dev && b->h->P.n)) return SYM_EINVAL;
+    if (!b->bound || !b->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    b->stream = s;
+    const sym::Plan &P = b->h->P;
+    const sym::DevicePlan &D = b->D;
+    if (P.n == 0) return SYM_OK;
+    if (sym::launch_perm_gather(P, D, bx_dev, D.vec, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_fwd(P, D, D.vec, D.vec2, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_bwd(P, D, D.vec2, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_perm_scatter(P, D, D.vec2, bx_dev, s) != hipSuccess) return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_batch_refine(sym_batch_t b, const double *Ax_dev, const double *b_dev, double *x_dev,
+                     int32_t steps, void *stream)
+{
+    if (!b || ((!Ax_dev || !b_dev || !x_dev) && b->h->P.n) || steps < 0) return SYM_EINVAL;
+    if (!b->bound || !b->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    const sym::Plan &P = b->h->P;
+    const sym::DevicePlan &D = b->D;
+    if (P.n == 0) return SYM_OK;
+    const size_t bytes = sizeof(double) * (size_t)P.n * (size_t)b->m;
+    if (hipMemcpyAsync(x_dev, b_dev, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SYM_EHIP;
+    int rc = sym_batch_solve(b, x_dev, stream);
+    if (rc != SYM_OK) return rc;
+    for (int32_t k = 0; k < steps; ++k) {
+        if (sym::launch_residual(P, D, Ax_dev, b_dev, x_dev, D.vec3, false, s) != hipSuccess) return SYM_EHIP;
+        rc = sym_batch_solve(b, D.vec3, stream);
+        if (rc != SYM_OK) return rc;
+        if (sym::launch_axpy(P, D, x_dev, D.vec3, s) != hipSuccess) return SYM_EHIP;
+    }
+    return SYM_OK;
+}
+
+int sym_batch_eta(sym_batch_t b, const double *Ax_dev, const double *b_dev, const double *x_dev,
+                  double *eta_host, void *stream)
+{
+    if (!b || !eta_host || ((!Ax_dev || !b_dev || !x_dev) && b->h->P.n)) return SYM_EINVAL;
+    if (!b->bound) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    const sym::Plan &P = b->h->P;
+    const sym::DevicePlan &D = b->D;
+    if (P.n == 0) {
+        for (int32_t i = 0; i < b->m; ++i) eta_host[i] = 0.0;
+        return SYM_OK;
+    }
+    if (sym::launch_residual(P, D, Ax_dev, b_dev, x_dev, D.vec3, true, s) != hipSuccess) return SYM_EHIP;
+    std::vector<double> red((size_t)b->m * 4);
+    if (hipMemcpyAsync(red.data(), D.red, sizeof(double) * red.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return SYM_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SYM_EHIP;
+    for (int32_t i = 0; i < b->m; ++i) {
+        const double *c = red.data() + 4 * (size_t)i;
+        const double den = c[1] * c[2] + c[3];
+        eta_host[i] = den > 0.0 ? c[0] / den : c[0];
+    }
+    return SYM_OK;
+}
+
+int sym_batch_status(sym_batch_t b, int64_t *info_host)
+{
+    if (!b || !info_host) return SYM_EINVAL;
+    if (!b->bound || !b->factored) return SYM_ESTATE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return SYM_EHIP;
+    std::vector<int32_t> w((size_t)b->m * 4);
+    if (hipMemcpy(w.data(), b->D.info, sizeof(int32_t) * w.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return SYM_EHIP;
+    int rc = SYM_OK;
+    for (int32_t i = 0; i < b->m; ++i) {
+        const int32_t *c = w.data() + 4 * (size_t)i;
+        if (c[1] != INT32_MAX || c[2] != 0) rc = SYM_ESCHED;
+        info_host[i] = c[0] == INT32_MAX ? 0 : 1 + (int64_t)b->h->P.perm[c[0]];
+    }
+    return rc;
+}
+
+void sym_batch_destroy(sym_batch_t b) { delete b; }
 
 }  // extern "C"

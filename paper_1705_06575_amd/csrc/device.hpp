@@ -11,7 +11,12 @@
 namespace sym {
 
 // Pointers into the caller's workspace, filled by sym_bind.
+// With m > 1 (a batch of value sets on one pattern) every per-instance
+// buffer below holds m consecutive copies (Lx: panel_entries each; the
+// vectors: n; info and red: 4; pend and done: nb; ticket: 16), and every
+// launch covers the m instances with its grid's second dimension.
 struct DevicePlan {
+    int32_t m = 1;                  // instances
     void *Lx = nullptr;             // panel values, double or float
     BlockDesc *blk = nullptr;       // nb
     int32_t *rows = nullptr;        // sum of supernode row counts
@@ -89,7 +94,7 @@ hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs
 hipError_t launch_residual(const Plan &P, const DevicePlan &D, const double *Ax, const double *b,
                            const double *x, double *r, bool with_anorm, hipStream_t s);
 // x += d
-hipError_t launch_axpy(const Plan &P, double *x, const double *d, hipStream_t s);
+hipError_t launch_axpy(const Plan &P, const DevicePlan &D, double *x, const double *d, hipStream_t s);
 // q = A p (FP64, full symmetric rows of A)
 hipError_t launch_spmv(const Plan &P, const DevicePlan &D, const double *Ax, const double *p,
                        double *q, hipStream_t s);

@@ -104,9 +104,13 @@ __device__ __forceinline__ void tile_out(T *__restrict__ dst, const T *src, int6
     }
 }
 
+// Kernels of the factorization take the value set (instance) of a batch
+// from blockIdx.y: its panels start lx_stride entries after the previous
+// instance's, its A values nnzA after, its status words 4 after.
 template <typename T>
 __global__ void k_fill_zero(T *__restrict__ x, int64_t count)
 {
+    x += blockIdx.y * count;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
         x[i] = T(0);
@@ -114,8 +118,10 @@ __global__ void k_fill_zero(T *__restrict__ x, int64_t count)
 
 template <typename T>
 __global__ void k_scatter_a(const double *__restrict__ Ax, const int64_t *__restrict__ amap,
-                            T *__restrict__ Lx, int64_t nnz)
+                            T *__restrict__ Lx, int64_t nnz, int64_t lx_stride)
 {
+    Ax += blockIdx.y * nnz;
+    Lx += blockIdx.y * lx_stride;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
          k += (int64_t)gridDim.x * blockDim.x)
         Lx[amap[k]] = (T)Ax[k];
@@ -123,6 +129,7 @@ __global__ void k_scatter_a(const double *__restrict__ Ax, const int64_t *__rest
 
 __global__ void k_info_reset(int32_t *info)
 {
+    info += 4 * blockIdx.y;
     info[0] = INT32_MAX;
     info[1] = INT32_MAX;
     info[2] = 0;
@@ -310,18 +317,21 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
     const int lane = threadIdx.x & 63;
     const int row = c0 + lane;
     const bool mine = row < nr;
-    T r[16];
+    // the diagonal factorization runs in FP64 whatever the storage type
+    // (for FP32 factors: FP64 pivots, reciprocal square roots and in-panel
+    // updates on the FP32 values, rounded once when stored)
+    double r[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? C[(c0 + c) * LDC + row] : T(0);
+    for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? (double)C[(c0 + c) * LDC + row] : 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const T d = lane_value(r[k], k);
-        if (k < wb && !(d > T(0)) && lane == 0) atomicMin(info, col0 + c0 + k);
-        const T inv = pivot_rsqrt(d);
+        const double d = lane_value(r[k], k);
+        if (k < wb && !(d > 0.0) && lane == 0) atomicMin(info, col0 + c0 + k);
+        const double inv = pivot_rsqrt(d);
         r[k] = lane == k ? d * inv : (lane > k ? r[k] * inv : r[k]);
 #pragma unroll
         for (int c = k + 1; c < 16; ++c) {
-            const T lck = lane_value(r[k], c);
+            const double lck = lane_value(r[k], c);
             r[c] = lane >= c ? r[c] - r[k] * lck : r[c];
         }
         // columns form a dependence chain anyway; keeping each column's
@@ -330,7 +340,7 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c)
-        if (mine && c < wb) C[(c0 + c) * LDC + row] = r[c];
+        if (mine && c < wb) C[(c0 + c) * LDC + row] = (T)r[c];
 }
 
 // One wavefront inverts the wb x wb lower triangle D[c0 .., c0 ..] (LDS,
@@ -741,10 +751,13 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
                                                  const WaveItem *__restrict__ witems,
                                                  const uint8_t *__restrict__ wmap,
                                                  const BlockDesc *__restrict__ blk,
-                                                 T *__restrict__ Lx, int32_t *__restrict__ info)
+                                                 T *__restrict__ Lx, int32_t *__restrict__ info,
+                                                 int64_t lx_stride)
 {
     __shared__ T C[64 * LDC];
     __shared__ T As[COOP ? 2 : 1][16][64];
+    Lx += blockIdx.y * lx_stride;
+    info += 4 * blockIdx.y;
     __shared__ T Bs[COOP ? 2 : 1][16][64];
     __shared__ int32_t s_rel[COOP ? 128 : 1];
 
@@ -793,8 +806,11 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
 template <typename T>
 __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
                                                  const BlockDesc *__restrict__ blk,
-                                                 T *__restrict__ Lx, int32_t *__restrict__ info)
+                                                 T *__restrict__ Lx, int32_t *__restrict__ info,
+                                                 int64_t lx_stride)
 {
+    Lx += blockIdx.y * lx_stride;
+    info += 4 * blockIdx.y;
     __shared__ T C[64 * LDC];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -870,8 +886,9 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
 template <typename T>
 __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
                                              const BlockDesc *__restrict__ blk,
-                                             T *__restrict__ Lx)
+                                             T *__restrict__ Lx, int64_t lx_stride)
 {
+    Lx += blockIdx.y * lx_stride;
     __shared__ T D[64 * LDC];
     __shared__ T X[64 * LDC];
     __shared__ T M[4 * 272];
@@ -925,30 +942,32 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
                        FactorProfile *prof)
 {
     T *Lx = (T *)D.Lx;
+    const unsigned m = (unsigned)D.m;
+    const int64_t lxs = P.panel_entries;
     if (prof) prof->used = 0;
     {
         Bracket b(prof, s, 0);
         if (P.panel_entries > 0)
-            k_fill_zero<T><<<grid_for(P.panel_entries), 256, 0, s>>>(Lx, P.panel_entries);
+            k_fill_zero<T><<<dim3(grid_for(P.panel_entries), m), 256, 0, s>>>(Lx, P.panel_entries);
         if (P.nnzA > 0)
-            k_scatter_a<T><<<grid_for(P.nnzA), 256, 0, s>>>(Ax, D.amap, Lx, P.nnzA);
-        k_info_reset<<<1, 1, 0, s>>>(D.info);
+            k_scatter_a<T><<<dim3(grid_for(P.nnzA), m), 256, 0, s>>>(Ax, D.amap, Lx, P.nnzA, lxs);
+        k_info_reset<<<dim3(1, m), 1, 0, s>>>(D.info);
     }
     for (const Phase &ph : P.phases) {
-        const unsigned g = (unsigned)(ph.t1 - ph.t0);
+        const dim3 g((unsigned)(ph.t1 - ph.t0), m);
         Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
             k_external<T, true><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                  D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                 D.wmap, D.blk, Lx, D.info);
+                                                 D.wmap, D.blk, Lx, D.info, lxs);
         else if (ph.kind == kPhaseExternal)
             k_external<T, false><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                   D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                  D.wmap, D.blk, Lx, D.info);
+                                                  D.wmap, D.blk, Lx, D.info, lxs);
         else if (ph.kind == kPhaseInternal)
-            k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info);
+            k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs);
         else
-            k_trsm<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx);
+            k_trsm<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, lxs);
     }
     return hipGetLastError();
 }

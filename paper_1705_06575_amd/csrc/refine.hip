@@ -30,9 +30,11 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Batched use: instance blockIdx.y owns 4 reduction words, its vectors
+// start n entries apart, its A values nnzA apart.
 __global__ void k_red_reset(double *red)
 {
-    if (threadIdx.x < 4) red[threadIdx.x] = 0.0;
+    if (threadIdx.x < 4) red[4 * blockIdx.y + threadIdx.x] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ rowptr,
@@ -42,8 +44,13 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
                                                   const double *__restrict__ b,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ r, double *__restrict__ red,
-                                                  int32_t n, int with_anorm)
+                                                  int32_t n, int with_anorm, int64_t nnzA)
 {
+    Ax += blockIdx.y * nnzA;
+    b += (int64_t)blockIdx.y * n;
+    x += (int64_t)blockIdx.y * n;
+    r += (int64_t)blockIdx.y * n;
+    red += 4 * blockIdx.y;
     double mr = 0.0, ma = 0.0, mx = 0.0, mb = 0.0;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0, sa = 0.0;
@@ -73,6 +80,8 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
 
 __global__ void k_axpy(double *__restrict__ x, const double *__restrict__ d, int32_t n)
 {
+    x += (int64_t)blockIdx.y * n;
+    d += (int64_t)blockIdx.y * n;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         x[i] += d[i];
 }
@@ -146,16 +155,17 @@ inline unsigned grid_for(int64_t count)
 hipError_t launch_residual(const Plan &P, const DevicePlan &D, const double *Ax, const double *b,
                            const double *x, double *r, bool with_anorm, hipStream_t s)
 {
-    k_red_reset<<<1, 64, 0, s>>>(D.red);
+    const unsigned m = (unsigned)D.m;
+    k_red_reset<<<dim3(1, m), 64, 0, s>>>(D.red);
     if (P.n > 0)
-        k_residual<<<grid_for(P.n), 256, 0, s>>>(D.arowptr, D.acol, D.aval, Ax, b, x, r, D.red,
-                                                  P.n, with_anorm ? 1 : 0);
+        k_residual<<<dim3(grid_for(P.n), m), 256, 0, s>>>(D.arowptr, D.acol, D.aval, Ax, b, x, r,
+                                                          D.red, P.n, with_anorm ? 1 : 0, P.nnzA);
     return hipGetLastError();
 }
 
-hipError_t launch_axpy(const Plan &P, double *x, const double *d, hipStream_t s)
+hipError_t launch_axpy(const Plan &P, const DevicePlan &D, double *x, const double *d, hipStream_t s)
 {
-    if (P.n > 0) k_axpy<<<grid_for(P.n), 256, 0, s>>>(x, d, P.n);
+    if (P.n > 0) k_axpy<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(x, d, P.n);
     return hipGetLastError();
 }
 

@@ -186,6 +186,8 @@ __device__ __forceinline__ double tri_backward(const double *D, double v, double
 __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict__ perm,
                          double *__restrict__ y, int32_t n)
 {
+    b += (int64_t)blockIdx.y * n;
+    y += (int64_t)blockIdx.y * n;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         y[i] = b[perm[i]];
 }
@@ -193,6 +195,8 @@ __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict
 __global__ void k_scatter_perm(const double *__restrict__ y, const int32_t *__restrict__ perm,
                                double *__restrict__ x, int32_t n)
 {
+    y += (int64_t)blockIdx.y * n;
+    x += (int64_t)blockIdx.y * n;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         x[perm[i]] = y[i];
 }
@@ -267,6 +271,9 @@ __device__ __forceinline__ bool wait_set(int32_t *p, int32_t *err)
 __global__ void k_sync_reset(int32_t *__restrict__ pend, const int32_t *__restrict__ init,
                              int32_t *__restrict__ done, int32_t nb, int32_t *__restrict__ ticket)
 {
+    pend += (int64_t)blockIdx.y * nb;
+    if (done) done += (int64_t)blockIdx.y * nb;
+    ticket += 16 * blockIdx.y;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
         pend[i] = init[i];
         if (done) done[i] = 0;
@@ -300,12 +307,20 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
                                                int32_t *err, const BlockDesc *__restrict__ blk,
                                                const int32_t *__restrict__ rows,
                                                const T *__restrict__ Lx, double *acc,
-                                               double *__restrict__ out)
+                                               double *__restrict__ out, int32_t n, int32_t nb,
+                                               int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
     __shared__ double ys[64];
     __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
+    // instance blockIdx.y of a batch
+    pend += (int64_t)blockIdx.y * nb;
+    ticket += 16 * blockIdx.y;
+    err += 4 * blockIdx.y;
+    Lx += blockIdx.y * lx_stride;
+    acc += (int64_t)blockIdx.y * n;
+    out += (int64_t)blockIdx.y * n;
     if (tid == 0) s_abort = 0;
     for (;;) {
         const int t = next_ticket(ticket, &s_t, ntasks, err);
@@ -366,11 +381,19 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
                                                int32_t *ticket, int32_t *err,
                                                const BlockDesc *__restrict__ blk,
                                                const int32_t *__restrict__ rows,
-                                               const T *__restrict__ Lx, double *x)
+                                               const T *__restrict__ Lx, double *x, int32_t n,
+                                               int32_t nb, int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
     __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
+    // instance blockIdx.y of a batch
+    pend += (int64_t)blockIdx.y * nb;
+    done += (int64_t)blockIdx.y * nb;
+    ticket += 16 * blockIdx.y;
+    err += 4 * blockIdx.y;
+    Lx += blockIdx.y * lx_stride;
+    x += (int64_t)blockIdx.y * n;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     if (tid == 0) s_abort = 0;
@@ -463,9 +486,9 @@ inline unsigned grid_for(int64_t count)
 
 // Workgroups of a persistent sweep: enough to fill the chip, at most one
 // per task.
-inline unsigned sweep_grid(int64_t ntasks)
+inline unsigned sweep_grid(int64_t ntasks, int32_t m)
 {
-    return (unsigned)std::min<int64_t>(ntasks, 2048);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntasks, 2048 / std::max(1, m)));
 }
 
 template <typename T>
@@ -473,10 +496,11 @@ hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, 
                     const int32_t *pend_init, double *acc, double *out, hipStream_t s)
 {
     if (ntasks == 0) return hipGetLastError();
-    k_sync_reset<<<grid_for(P.nb), 256, 0, s>>>(D.pend, pend_init, nullptr, P.nb, D.ticket);
-    k_fwd_df<T><<<sweep_grid(ntasks), NT, 0, s>>>(tasks, (int)ntasks, D.chunk_tptr, D.chunk_tgt,
-                                                   D.pend, D.ticket, D.info + 2, D.blk, D.rows,
-                                                   (const T *)D.Lx, acc, out);
+    const unsigned m = (unsigned)D.m;
+    k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, pend_init, nullptr, P.nb, D.ticket);
+    k_fwd_df<T><<<dim3(sweep_grid(ntasks, D.m), m), NT, 0, s>>>(
+        tasks, (int)ntasks, D.chunk_tptr, D.chunk_tgt, D.pend, D.ticket, D.info + 2, D.blk, D.rows,
+        (const T *)D.Lx, acc, out, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }
 
@@ -485,10 +509,11 @@ hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s
 {
     const int64_t ntasks = (int64_t)P.bwd_df.size();
     if (ntasks == 0) return hipGetLastError();
-    k_sync_reset<<<grid_for(P.nb), 256, 0, s>>>(D.pend, D.bwd_pend, D.done, P.nb, D.ticket);
-    k_bwd_df<T><<<sweep_grid(ntasks), NT, 0, s>>>(D.bwd_df, (int)ntasks, D.chunk_tptr, D.chunk_tgt,
-                                                   D.pend, D.done, D.ticket, D.info + 2, D.blk,
-                                                   D.rows, (const T *)D.Lx, y);
+    const unsigned m = (unsigned)D.m;
+    k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, D.bwd_pend, D.done, P.nb, D.ticket);
+    k_bwd_df<T><<<dim3(sweep_grid(ntasks, D.m), m), NT, 0, s>>>(
+        D.bwd_df, (int)ntasks, D.chunk_tptr, D.chunk_tgt, D.pend, D.done, D.ticket, D.info + 2,
+        D.blk, D.rows, (const T *)D.Lx, y, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }
 
@@ -497,14 +522,14 @@ hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s
 hipError_t launch_perm_gather(const Plan &P, const DevicePlan &D, const double *b, double *y,
                               hipStream_t s)
 {
-    if (P.n > 0) k_gather<<<grid_for(P.n), 256, 0, s>>>(b, D.perm, y, P.n);
+    if (P.n > 0) k_gather<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(b, D.perm, y, P.n);
     return hipGetLastError();
 }
 
 hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double *y, double *x,
                                hipStream_t s)
 {
-    if (P.n > 0) k_scatter_perm<<<grid_for(P.n), 256, 0, s>>>(y, D.perm, x, P.n);
+    if (P.n > 0) k_scatter_perm<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(y, D.perm, x, P.n);
     return hipGetLastError();
 }
 
