@@ -176,6 +176,73 @@ def stored_traffic(kernel: str):
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
+def batched(dev, steps: int = 4, reps: int = 3, tune_m: int = 4):
+    """The batched workload: 512 value sets on the 2-D 9-point 128^2 pattern
+    plus 64 each on the 3-D 7-point 24^3 and 40^3 patterns (per-instance
+    weights log-uniform in [1e-2, 1e2], A = L_G(w) + 1e-3 I), FP32 factors
+    + `steps` FP64 refinement steps for every instance, all captured in one
+    HIP graph and timed per replay.  Each pattern's block width and
+    amalgamation are picked by the autotuner (timed on tune_m instances)."""
+    import numpy as np
+    import torch
+
+    import paper_1705_06575_amd as S
+    from paper_1705_06575_amd import autotune
+    import workloads as W
+    groups, out = [], {"workload": "512 x grid2d_9pt_128^2 + 64 x grid3d_7pt_24^3 + 64 x grid3d_7pt_40^3, "
+                                   "FP32 factor + FP64 refinement, one graph", "steps": steps,
+                       "groups": []}
+    flops = 0.0
+    for kind, m in (("9pt128", 512), ("7pt24", 64), ("7pt40", 64)):
+        n, Ap, Ai, X, perm = W.config4_batch(kind, m)
+        vals = torch.from_numpy(X).to(dev)
+        best, table = autotune.tune(n, Ap, Ai, vals[:tune_m].contiguous(), ordering=perm,
+                                    precision="f32", reps=2)
+        an = S.Analysis(n, Ap, Ai, ordering=perm, precision="f32", **best)
+        an.bind(dev)
+        bt = S.Batch(an, m)
+        B = torch.from_numpy(np.random.default_rng(20261000).uniform(-1.0, 1.0, (m, n))).to(dev)
+        groups.append(dict(an=an, bt=bt, vals=vals, B=B, X=torch.empty_like(B)))
+        flops += m * an.stat("flops")
+        out["groups"].append({"pattern": kind, "instances": m, "n": n, "nnz_L": int(an.stat("nnzL")),
+                              "tuned": best, "tune_ms": {f"B{t['block_width']}{'a' if t['amalgamate'] else ''}":
+                                                         round(t["ms"], 3) for t in table}})
+
+    def run():
+        for g in groups:
+            g["bt"].factor(g["vals"])
+            g["bt"].refine(g["vals"], g["B"], g["X"], steps)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    graph.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = _events(torch)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    etas = [float(g["bt"].eta(g["vals"], g["B"], g["X"]).max()) for g in groups]
+    bad = [int((g["bt"].status() != 0).sum()) for g in groups]
+    out.update({"graph_ms": round(ms, 2), "factor_flops": flops,
+                "gflops_fp64_equiv": round(flops / (ms * 1e-3) / 1e9, 1),
+                "max_eta_inf": max(etas), "failed_instances": sum(bad)})
+    for g in groups:
+        g["bt"].close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +252,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64 vs FP32+refinement comparison")
     ap.add_argument("--mixed-m", type=int, default=80, help="grid side of the mixed-precision workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched graph workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (byte-counter calibration)")
     ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -337,6 +405,9 @@ def main():
         del an, rp
         torch.cuda.empty_cache()
         out["mixed_ir"] = mixed_ir(dev, args.mixed_m)
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        out["batched"] = batched(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -278,6 +278,32 @@ def config4_instance(kind: str, k: int) -> Workload:
     raise ValueError(kind)
 
 
+_CONFIG4_SHAPES = {"9pt128": ((128, 128), True), "7pt24": ((24, 24, 24), False),
+                   "7pt40": ((40, 40, 40), False)}
+
+
+def config4_batch(kind: str, m: int, k0: int = 0):
+    """Instances k0 .. k0+m-1 of config4_instance(kind, k) at once: the
+    shared pattern (n, Ap, Ai), the grid's ordering, and the m value sets
+    as an (m, nnz) array (each row equal to that instance's Ax)."""
+    shape, full = _CONFIG4_SHAPES[kind]
+    n = int(np.prod(shape))
+    hi, lo = _stencil_edges(shape, _half_offsets(len(shape), full=full))
+    rows = np.concatenate([np.arange(n, dtype=np.int64), hi.astype(np.int64)])
+    cols = np.concatenate([np.arange(n, dtype=np.int64), lo.astype(np.int64)])
+    order = np.lexsort((rows, cols))
+    Ap = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(Ap, cols + 1, 1)
+    Ap = np.cumsum(Ap)
+    Ai = rows[order].astype(np.int32)
+    X = np.empty((m, order.size))
+    for j in range(m):
+        w = _log_uniform(rng_for_instance(k0 + j), 1e-2, 1e2, hi.size)
+        rowsum = np.bincount(hi, w, minlength=n) + np.bincount(lo, w, minlength=n)
+        X[j] = np.concatenate([rowsum + 1e-3, -w])[order]
+    return n, Ap, Ai, X, grid_nd_order(shape)
+
+
 def random_spd_3x3(rng, count):
     """count random SPD 3x3 blocks Q diag(lambda) Q^T, Q Haar, lambda ~ U[0.1, 10]."""
     g = rng.standard_normal((count, 3, 3))
