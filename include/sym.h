@@ -205,6 +205,10 @@ int sym_export_factor(sym_handle h, double *Lx_host, void *stream);
 #define SYM_GET_SPARENT 7     /* int32[ns]  supernodal elimination tree */
 #define SYM_GET_BLOCKS 8      /* int32[nb+1] first column of each device block, then n */
 #define SYM_GET_BLEVEL 9      /* int32[nb]  level of each block (leaves 0) */
+#define SYM_GET_SUPER_FEAT 10 /* double[nds*8] features of each device supernode (see below) */
+#define SYM_GET_TASK_SUPER 11 /* int32[ntasks] device supernode an external-update task
+                                 updates, -1 for the factor's other tasks */
+#define SYM_GET_VARIANT 12    /* uint8[nds] kernel variant of each device supernode */
 int sym_get_size(sym_handle h, int what, int64_t *count);
 int sym_get(sym_handle h, int what, void *out);
 
@@ -244,6 +248,58 @@ int sym_stat(sym_handle h, int what, double *value);
 #define SYM_PROFILE_KINDS 4
 int sym_profile(sym_handle h, int enable);
 int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algorithmic_flops);
+
+/*
+ * Per-supernode kernel variants (the choices a cost model makes).  The
+ * external update of device supernode s (nds = SYM_STAT_NDSUPER of them)
+ * runs its incidences -- (row tile, descendant) products -- either all as
+ * per-wavefront items (variant 0) or, for those with at least 32 (variant
+ * 1, the default) or 16 (variant 2) rows, columns and inner indices, on
+ * the whole workgroup through LDS.  Results do not depend on the variant
+ * beyond rounding order.  SYM_GET_SUPER_FEAT gives 8 features per device
+ * supernode: width, rows, row tiles receiving updates, incidences
+ * received, their product flops, the fractions of those flops in
+ * incidences of >= 32 and >= 16 rows, columns and inner indices, level.
+ *
+ * sym_set_variants: variant[nds] (values 0..2) for every device supernode;
+ * rebuilds the schedule on the host, so the workspace size may change and
+ * the handle must be bound again (it is left unbound).  Errors:
+ * SYM_EINVAL (count != nds or a value > 2).
+ *
+ * sym_task_times: for the most recent sym_factor run with profiling
+ * enabled (sym_profile), the duration in microseconds of every factor
+ * task's workgroup (us[ntasks], ntasks = SYM_GET_TASK_SUPER's count);
+ * external-update tasks only, the others read 0.  Synchronizes.  Errors:
+ * SYM_EINVAL, SYM_ESTATE (not bound), SYM_EHIP.
+ */
+int sym_set_variants(sym_handle h, const uint8_t *variant, int32_t count);
+int sym_task_times(sym_handle h, double *us);
+
+/*
+ * The cost model's network (the learned part of kernel-variant selection):
+ * fully connected, FP32, d_in inputs (1..32), two hidden layers of
+ * SYM_MLP_HIDDEN ReLU units, one linear output.  Parameters are one flat
+ * device float array of sym_mlp_param_count(d_in) entries: W1[64][d_in]
+ * (row j = unit j's input weights), b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Samples: X_dev float[n][d_in] row-major; targets and outputs float[n].
+ *
+ * sym_mlp_forward: y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 per sample.
+ * sym_mlp_backward: grad_dev = the gradient, with respect to every
+ * parameter, of the mean squared error (1/n) sum (y - t)^2; work_dev:
+ * caller scratch of n * (4 * 64 + 1) floats.  Each gradient entry is a sum
+ * over samples in sample order (bitwise reproducible).
+ * sym_mlp_adam: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step
+ * counted from 1) on params_dev with moment buffers m_dev, v_dev.
+ * All run on `stream` without synchronizing.  Errors: SYM_EINVAL, SYM_EHIP.
+ */
+#define SYM_MLP_HIDDEN 64
+int sym_mlp_param_count(int32_t d_in, int64_t *count);
+int sym_mlp_forward(const float *params_dev, const float *X_dev, int32_t n, int32_t d_in,
+                    float *y_dev, void *stream);
+int sym_mlp_backward(const float *params_dev, const float *X_dev, const float *t_dev, int32_t n,
+                     int32_t d_in, float *grad_dev, float *work_dev, void *stream);
+int sym_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                 int64_t count, int32_t step, float lr, void *stream);
 
 /*
  * Batches: m value sets on the pattern of one analysis (Section 1.2: the

@@ -24,9 +24,11 @@ _ERRORS = {
     -5: "SYM_ESTATE", -6: "SYM_EWORKSPACE", -7: "SYM_ESCHED",
 }
 
-GET = dict(perm=1, parent=2, colcount=3, Lp=4, Li=5, super=6, sparent=7, blocks=8, blevel=9)
+GET = dict(perm=1, parent=2, colcount=3, Lp=4, Li=5, super=6, sparent=7, blocks=8, blevel=9,
+           super_feat=10, task_super=11, variant=12)
 GET_DTYPE = dict(perm=np.int32, parent=np.int32, colcount=np.int64, Lp=np.int64, Li=np.int32,
-                 super=np.int32, sparent=np.int32, blocks=np.int32, blevel=np.int32)
+                 super=np.int32, sparent=np.int32, blocks=np.int32, blevel=np.int32,
+                 super_feat=np.float64, task_super=np.int32, variant=np.uint8)
 STAT = dict(n=1, nnzA=2, nnzL=3, flops=4, nsuper=5, nblocks=6, nlevels=7, npairs=8,
             panel_entries=9, analyze_ms=10, sum_rows=11, nphases=12, nincidences=13,
             nslevels=14, ndsuper=15, stored_lower=16)
@@ -56,7 +58,8 @@ EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_
            "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
            "sym_rhs_destroy", "sym_batch_create", "sym_batch_workspace", "sym_batch_bind",
            "sym_batch_factor", "sym_batch_solve", "sym_batch_refine", "sym_batch_eta",
-           "sym_batch_status", "sym_batch_destroy"]
+           "sym_batch_status", "sym_batch_destroy", "sym_set_variants", "sym_task_times", "sym_mlp_param_count", "sym_mlp_forward",
+           "sym_mlp_backward", "sym_mlp_adam"]
 
 _lib = None
 
@@ -106,6 +109,12 @@ def load_library(path: str = LIB_PATH):
     L.sym_batch_refine.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp]
     L.sym_batch_eta.argtypes = [vp, vp, vp, vp, vp, vp]
     L.sym_batch_status.argtypes = [vp, vp]
+    L.sym_mlp_param_count.argtypes = [ctypes.c_int32, ctypes.POINTER(i64)]
+    L.sym_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    L.sym_mlp_backward.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    L.sym_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_float, vp]
+    L.sym_set_variants.argtypes = [vp, vp, ctypes.c_int32]
+    L.sym_task_times.argtypes = [vp, vp]
     L.sym_batch_destroy.restype = None
     L.sym_batch_destroy.argtypes = [vp]
     no_ret = ("sym_opts_default", "sym_destroy", "sym_rhs_destroy", "sym_batch_destroy")
@@ -215,6 +224,26 @@ class Analysis:
         v = ctypes.c_double()
         _check("sym_stat", self._lib.sym_stat(self._h, STAT[what], ctypes.byref(v)))
         return v.value
+
+    def set_variants(self, variant):
+        """Per-device-supernode kernel variants (0..2); the analysis is
+        unbound afterwards and binds again on its next device call."""
+        v = np.ascontiguousarray(variant, dtype=np.uint8)
+        _check("sym_set_variants", self._lib.sym_set_variants(self._h, _ptr(v), int(v.size)))
+        self._ws = None
+        self._factored = False
+
+    def task_times(self) -> np.ndarray:
+        """Workgroup duration (us) of every factor task of the last profiled
+        factorization (external-update tasks; others 0)."""
+        out = np.zeros(max(int(self.get_size("task_super")), 1))
+        _check("sym_task_times", self._lib.sym_task_times(self._h, _ptr(out)))
+        return out[:int(self.get_size("task_super"))]
+
+    def get_size(self, what: str) -> int:
+        cnt = ctypes.c_int64()
+        _check("sym_get_size", self._lib.sym_get_size(self._h, GET[what], ctypes.byref(cnt)))
+        return cnt.value
 
     @property
     def workspace_bytes(self) -> int:

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libsym.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HOST_SOURCES = ["symbolic.cpp", "ordering.cpp", "capi.cpp"]
-DEVICE_SOURCES = ["factor.hip", "solve.hip", "refine.hip"]
+DEVICE_SOURCES = ["factor.hip", "solve.hip", "refine.hip", "mlp.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # gfx950 only; packed FP32 instructions are disabled for every device pass

@@ -20,7 +20,7 @@ struct sym_plan {
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
-           off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0,
+           off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
            off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -91,6 +91,7 @@ void layout(sym_plan *h)
     h->off_vec5 = take(sizeof(double) * (size_t)P.n);
     h->off_vec6 = take(sizeof(double) * (size_t)P.n);
     h->off_part = take(sizeof(double) * (sym::kDotParts + 8));
+    h->off_ttime = take(sizeof(uint64_t) * P.ftasks.size());
     h->ws_bytes = o;
 }
 
@@ -195,6 +196,7 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.vec5 = (double *)(base + h->off_vec5);
     D.vec6 = (double *)(base + h->off_vec6);
     D.part = (double *)(base + h->off_part);
+    D.ttime = (uint64_t *)(base + h->off_ttime);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
@@ -221,6 +223,8 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.fwd_pend, P.fwd_pend.data(), sizeof(int32_t) * P.fwd_pend.size(), s);
     if (e == hipSuccess) e = upload(D.bwd_pend, P.bwd_pend.data(), sizeof(int32_t) * P.bwd_pend.size(), s);
     if (e == hipSuccess) e = upload(D.bwd_df, P.bwd_df.data(), sizeof(sym::SolveTask) * P.bwd_df.size(), s);
+    if (e == hipSuccess && !P.ftasks.empty())
+        e = hipMemsetAsync(D.ttime, 0, sizeof(uint64_t) * P.ftasks.size(), s);
     if (e == hipSuccess) e = upload(D.arowptr, P.arowptr.data(), sizeof(int64_t) * P.arowptr.size(), s);
     if (e == hipSuccess) e = upload(D.acol, P.acol.data(), sizeof(int32_t) * P.acol.size(), s);
     if (e == hipSuccess) e = upload(D.aval, P.aval.data(), sizeof(int64_t) * P.aval.size(), s);
@@ -317,6 +321,38 @@ int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *
     }
     if (iters) *iters = it;
     if (eta) *eta = e;
+    return SYM_OK;
+}
+
+int sym_set_variants(sym_handle h, const uint8_t *variant, int32_t count)
+{
+    if (!h || (!variant && count) || count != h->P.nds) return SYM_EINVAL;
+    for (int32_t s2 = 0; s2 < count; ++s2)
+        if (variant[s2] >= sym::kVariants) return SYM_EINVAL;
+    try {
+        h->P.svariant.assign(variant, variant + count);
+        sym::build_schedule(h->P);
+    } catch (const std::bad_alloc &) {
+        return SYM_ENOMEM;
+    }
+    layout(h);
+    h->bound = false;
+    h->factored = false;
+    return SYM_OK;
+}
+
+int sym_task_times(sym_handle h, double *us)
+{
+    if (!h || (!us && !h->P.ftasks.empty())) return SYM_EINVAL;
+    if (!h->bound) return SYM_ESTATE;
+    const size_t nt = h->P.ftasks.size();
+    if (nt == 0) return SYM_OK;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return SYM_EHIP;
+    std::vector<uint64_t> ticks(nt);
+    if (hipMemcpy(ticks.data(), h->D.ttime, sizeof(uint64_t) * nt, hipMemcpyDeviceToHost) != hipSuccess)
+        return SYM_EHIP;
+    // the device's constant wall clock runs at 100 MHz
+    for (size_t q = 0; q < nt; ++q) us[q] = (double)ticks[q] * 0.01;
     return SYM_OK;
 }
 
@@ -545,6 +581,9 @@ int sym_get_size(sym_handle h, int what, int64_t *count)
     case SYM_GET_SPARENT: *count = P.ns; break;
     case SYM_GET_BLOCKS: *count = (int64_t)P.nb + 1; break;
     case SYM_GET_BLEVEL: *count = P.nb; break;
+    case SYM_GET_SUPER_FEAT: *count = (int64_t)P.nds * sym::kSuperFeatures; break;
+    case SYM_GET_TASK_SUPER: *count = (int64_t)P.ftasks.size(); break;
+    case SYM_GET_VARIANT: *count = P.nds; break;
     default: return SYM_EINVAL;
     }
     return SYM_OK;
@@ -556,6 +595,11 @@ int sym_get(sym_handle h, int what, void *out)
     const sym::Plan &P = h->P;
     switch (what) {
     case SYM_GET_PERM: std::memcpy(out, P.perm.data(), sizeof(int32_t) * P.perm.size()); break;
+    case SYM_GET_SUPER_FEAT: std::memcpy(out, P.sfeat.data(), sizeof(double) * P.sfeat.size()); break;
+    case SYM_GET_TASK_SUPER:
+        std::memcpy(out, P.task_super.data(), sizeof(int32_t) * P.task_super.size());
+        break;
+    case SYM_GET_VARIANT: std::memcpy(out, P.svariant.data(), P.svariant.size()); break;
     case SYM_GET_PARENT: std::memcpy(out, P.parent.data(), sizeof(int32_t) * P.parent.size()); break;
     case SYM_GET_COLCOUNT: std::memcpy(out, P.colcount.data(), sizeof(int64_t) * P.colcount.size()); break;
     case SYM_GET_LP: {
@@ -671,6 +715,43 @@ int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algori
 void sym_destroy(sym_handle h) { delete h; }
 void sym_rhs_destroy(sym_rhs r) { delete r; }
 
+
+// ------------------------------------------------------------ cost model
+
+int sym_mlp_param_count(int32_t d_in, int64_t *count)
+{
+    if (!count || d_in < 1 || d_in > sym::kMlpMaxIn) return SYM_EINVAL;
+    *count = sym::mlp_param_count(d_in);
+    return SYM_OK;
+}
+
+int sym_mlp_forward(const float *params_dev, const float *X_dev, int32_t n, int32_t d_in,
+                    float *y_dev, void *stream)
+{
+    if (d_in < 1 || d_in > sym::kMlpMaxIn || n < 0 || !params_dev || (n && (!X_dev || !y_dev)))
+        return SYM_EINVAL;
+    return sym::launch_mlp_forward(params_dev, X_dev, n, d_in, y_dev, (hipStream_t)stream) == hipSuccess
+               ? SYM_OK : SYM_EHIP;
+}
+
+int sym_mlp_backward(const float *params_dev, const float *X_dev, const float *t_dev, int32_t n,
+                     int32_t d_in, float *grad_dev, float *work_dev, void *stream)
+{
+    if (d_in < 1 || d_in > sym::kMlpMaxIn || n < 1 || !params_dev || !X_dev || !t_dev || !grad_dev ||
+        !work_dev)
+        return SYM_EINVAL;
+    return sym::launch_mlp_backward(params_dev, X_dev, t_dev, n, d_in, grad_dev, work_dev,
+                                    (hipStream_t)stream) == hipSuccess ? SYM_OK : SYM_EHIP;
+}
+
+int sym_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                 int64_t count, int32_t step, float lr, void *stream)
+{
+    if (!params_dev || !grad_dev || !m_dev || !v_dev || count < 1 || step < 1 || !(lr > 0.0f))
+        return SYM_EINVAL;
+    return sym::launch_mlp_adam(params_dev, grad_dev, m_dev, v_dev, count, step, lr,
+                                (hipStream_t)stream) == hipSuccess ? SYM_OK : SYM_EHIP;
+}
 
 // ------------------------------------------------------------------ batches
 

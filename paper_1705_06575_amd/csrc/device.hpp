@@ -45,6 +45,7 @@ struct DevicePlan {
     double *vec5 = nullptr;         // n scratch: A p
     double *vec6 = nullptr;         // n scratch: preconditioned residual z
     double *part = nullptr;         // kDotParts partial sums of a dot product
+    uint64_t *ttime = nullptr;      // tasks: duration of each profiled external task (100 MHz ticks)
     // dataflow sweeps
     int64_t *chunk_tptr = nullptr;  // fwd tasks+1
     int32_t *chunk_tgt = nullptr;   // target blocks of each chunk
@@ -106,5 +107,17 @@ hipError_t launch_dot(const Plan &P, const DevicePlan &D, const double *u, const
 hipError_t launch_axpy_s(const Plan &P, double *y, double a, const double *x, hipStream_t s);
 // p = z + b p
 hipError_t launch_xpby(const Plan &P, double *p, const double *z, double b, hipStream_t s);
+
+// ---- cost-model network (mlp.hip)
+constexpr int kMlpHidden = 64;      // units per hidden layer
+constexpr int kMlpMaxIn = 32;       // input features at most
+int64_t mlp_param_count(int D);
+hipError_t launch_mlp_forward(const float *params, const float *X, int n, int D, float *y,
+                              hipStream_t s);
+// grad = gradient of the mean squared error; work: n * (4 * kMlpHidden + 1) floats
+hipError_t launch_mlp_backward(const float *params, const float *X, const float *t, int n, int D,
+                               float *grad, float *work, hipStream_t s);
+hipError_t launch_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,
+                           int step, float lr, hipStream_t s);
 
 }  // namespace sym

@@ -752,8 +752,10 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
                                                  const uint8_t *__restrict__ wmap,
                                                  const BlockDesc *__restrict__ blk,
                                                  T *__restrict__ Lx, int32_t *__restrict__ info,
-                                                 int64_t lx_stride)
+                                                 int64_t lx_stride,
+                                                 unsigned long long *__restrict__ ttime)
 {
+    const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
     __shared__ T C[64 * LDC];
     __shared__ T As[COOP ? 2 : 1][16][64];
     Lx += blockIdx.y * lx_stride;
@@ -796,6 +798,10 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
     if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
 
     tile_out(LJ + r0, C, J.ld, nr, w);
+    if (ttime && blockIdx.y == 0) {
+        __syncthreads();                    // every wavefront's work is issued
+        if (threadIdx.x == 0) ttime[blockIdx.x] = wall_clock64() - t_start;
+    }
 }
 
 // Internal (right-looking) update of one row tile of block J by the final
@@ -944,6 +950,10 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
     T *Lx = (T *)D.Lx;
     const unsigned m = (unsigned)D.m;
     const int64_t lxs = P.panel_entries;
+    // per-task durations are recorded while profiling a single factorization
+    auto ttime = [&](const Phase &ph) {
+        return (prof && D.ttime && D.m == 1) ? (unsigned long long *)(D.ttime + ph.t0) : nullptr;
+    };
     if (prof) prof->used = 0;
     {
         Bracket b(prof, s, 0);
@@ -959,11 +969,11 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
             k_external<T, true><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                  D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                 D.wmap, D.blk, Lx, D.info, lxs);
+                                                 D.wmap, D.blk, Lx, D.info, lxs, ttime(ph));
         else if (ph.kind == kPhaseExternal)
             k_external<T, false><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                   D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                  D.wmap, D.blk, Lx, D.info, lxs);
+                                                  D.wmap, D.blk, Lx, D.info, lxs, ttime(ph));
         else if (ph.kind == kPhaseInternal)
             k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs);
         else

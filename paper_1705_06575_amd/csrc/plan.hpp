@@ -81,10 +81,14 @@ static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the devi
 
 constexpr int32_t kFuseFactor = 1;
 
-// An incidence is "large" -- multiplied by the whole workgroup through LDS
-// -- when its product has at least this many rows, columns and inner
-// indices.
-constexpr int32_t kLargeRows = 32, kLargeCols = 32, kLargeInner = 32;
+// Kernel variant of a target supernode's external update: an incidence is
+// "large" -- multiplied by the whole workgroup through LDS -- when its
+// product has at least kVariantLarge[v] rows, columns and inner indices;
+// the others run as per-wavefront items.  Variant 0 puts every incidence on
+// the per-wavefront path, 1 (the default) uses 32, 2 uses 16.
+constexpr int kVariants = 3;
+constexpr int32_t kVariantLarge[kVariants] = {1 << 30, 32, 16};
+constexpr int kSuperFeatures = 8;   // features of a device supernode, see Plan::sfeat
 
 // One kernel launch of the factorization.
 enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2 };
@@ -159,6 +163,15 @@ struct Plan {
     std::vector<int32_t> bwd_pend;      // nb: off-diagonal chunks of the block
     std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers, then diagonals
 
+    // per device supernode: kernel variant of its external update, and the
+    // features a cost model sees (kSuperFeatures each): width, rows, row
+    // tiles of its blocks, incidences it receives, their product flops,
+    // the fractions of those flops in incidences of >= 32 and >= 16 rows,
+    // columns and inner indices, and its level
+    std::vector<uint8_t> svariant;
+    std::vector<double> sfeat;
+    std::vector<int32_t> task_super;    // ftasks.size(): target supernode of external tasks, else -1
+
     // descendant pairs, grouped by target block
     std::vector<int64_t> dptr;      // nb+1
     std::vector<Pair> pairs;
@@ -202,6 +215,9 @@ struct Plan {
 // Analysis entry point (symbolic.cpp).  Returns SYM_OK or a SYM_E* code.
 int analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, int ordering,
             const int32_t *user_perm, int block_width, int nd_leaf, bool relax, Plan &P);
+
+// Factor schedule for the plan's current svariant (symbolic.cpp).
+void build_schedule(Plan &P);
 
 // Graph nested dissection on the symmetric pattern (ordering.cpp).
 // adj: CSR adjacency without self loops.  Returns perm[new] = old.

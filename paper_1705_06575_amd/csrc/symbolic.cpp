@@ -62,6 +62,249 @@ void permute_lower(int32_t n, const int64_t *Ap, const int32_t *Ai,
 
 }  // namespace
 
+// The factor schedule of a plan (tasks, launches, incidences and
+// per-wavefront items) for its current per-supernode kernel variants;
+// rerun whenever the variants change.
+void build_schedule(Plan &P)
+{
+    const int32_t B = P.B;
+    if ((int32_t)P.svariant.size() != P.nds) P.svariant.assign((size_t)P.nds, 1);
+    P.sfeat.assign((size_t)P.nds * kSuperFeatures, 0.0);
+    P.sbptr.assign((size_t)P.nds + 1, 0);
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) {
+        int32_t w = P.dsptr[s2 + 1] - P.dsptr[s2];
+        P.sbptr[s2 + 1] = P.sbptr[s2] + (w + B - 1) / B;
+    }
+    P.slevel.assign((size_t)P.nds, 0);
+    for (int32_t s2 = 0; s2 < P.nds; ++s2)
+        if (P.dsparent[s2] >= 0)
+            P.slevel[P.dsparent[s2]] = std::max(P.slevel[P.dsparent[s2]], P.slevel[s2] + 1);
+    P.nslevels = 0;
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) P.nslevels = std::max(P.nslevels, P.slevel[s2] + 1);
+    std::vector<int32_t> sl_ptr((size_t)P.nslevels + 1, 0), sl_list((size_t)P.nds);
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) sl_ptr[P.slevel[s2] + 1]++;
+    for (int32_t l = 0; l < P.nslevels; ++l) sl_ptr[l + 1] += sl_ptr[l];
+    {
+        std::vector<int32_t> fill(sl_ptr.begin(), sl_ptr.end() - 1);
+        for (int32_t s2 = 0; s2 < P.nds; ++s2) sl_list[fill[P.slevel[s2]]++] = s2;
+    }
+    auto ntiles = [&](int32_t J) { return (P.blk[J].r + kTileRows - 1) / kTileRows; };
+    P.ftasks.clear();
+    P.phases.clear();
+    P.incs.clear();
+    P.iptr.assign(1, 0);
+    std::vector<int32_t> blk2ds((size_t)P.nb);
+    for (int32_t r = 0; r < P.nds; ++r)
+        for (int32_t b = P.sbptr[r]; b < P.sbptr[r + 1]; ++b) blk2ds[b] = r;
+    // K is a block; a descendant supernode's blocks share their rows below
+    // its columns, so all of its blocks' contributions to a tile form one
+    // product whose inner dimension is the supernode's width (wk)
+    struct RawInc { int32_t K, a0, a1, b0, b1, wk; };
+    std::vector<std::vector<RawInc>> per_tile;
+    P.imap.clear();
+    P.ibig.clear();
+    P.wptr.assign(1, 0);
+    P.witems.clear();
+    P.wmap.clear();
+    // tasks without wavefront items push their (empty) ranges here
+    auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags, int64_t big_end) {
+        P.ftasks.push_back(Task{J, t, K, flags});
+        P.iptr.push_back((int64_t)P.incs.size());
+        P.ibig.push_back(big_end);
+        while ((int64_t)P.wptr.size() < 4 * (int64_t)P.ftasks.size() + 1)
+            P.wptr.push_back((int64_t)P.witems.size());
+    };
+    // tile rows of K's rows [b0, b1) and tile columns of K's rows [a0, a1)
+    std::vector<uint8_t> rrel, crel;
+    auto relative = [&](int32_t J, int32_t t, const RawInc &ri) {
+        const BlockDesc &dJ = P.blk[J];
+        const BlockDesc &dK = P.blk[ri.K];
+        const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
+        const int32_t *rK = P.dsrows.data() + dK.rowoff;
+        const int32_t r0 = t * kTileRows;
+        const int32_t nr = std::min(kTileRows, dJ.r - r0);
+        rrel.clear();
+        crel.clear();
+        int32_t p = r0;
+        for (int32_t q = ri.b0; q < ri.b1; ++q) {
+            while (p < r0 + nr && rJ[p] < rK[q]) ++p;
+            rrel.push_back((uint8_t)(p - r0));
+        }
+        for (int32_t q = ri.a0; q < ri.a1; ++q) crel.push_back((uint8_t)(rK[q] - dJ.col0));
+    };
+    // the wavefront items of one task's small incidences, wavefront-major
+    auto emit_wave_items = [&](int32_t J, int32_t t, const std::vector<const RawInc *> &small) {
+        for (int32_t v = 0; v < 4; ++v) {
+            for (const RawInc *ri : small) {
+                relative(J, t, *ri);
+                // columns are increasing: the wavefront's are a contiguous run
+                int32_t jlo = 0, jhi = 0;
+                while (jlo < (int32_t)crel.size() && crel[jlo] < 16 * v) ++jlo;
+                jhi = jlo;
+                while (jhi < (int32_t)crel.size() && crel[jhi] < 16 * v + 16) ++jhi;
+                if (jlo == jhi) continue;
+                WaveItem it{};
+                it.valoff = P.blk[ri->K].valoff;
+                it.mapoff = (int64_t)P.wmap.size();
+                it.ld = P.blk[ri->K].ld;
+                it.b0 = ri->b0;
+                it.a0 = ri->a0 + jlo;
+                it.wk = (int16_t)ri->wk;
+                it.nI = (uint8_t)rrel.size();
+                it.nJ = (uint8_t)(jhi - jlo);
+                P.wmap.insert(P.wmap.end(), rrel.begin(), rrel.end());
+                P.wmap.insert(P.wmap.end(), crel.begin() + jlo, crel.begin() + jhi);
+                P.witems.push_back(it);
+            }
+            P.wptr.push_back((int64_t)P.witems.size());
+        }
+    };
+    auto open_phase = [&](int32_t kind) { P.phases.push_back(Phase{kind, (int64_t)P.ftasks.size(), 0}); };
+    auto close_phase = [&]() {
+        P.phases.back().t1 = (int64_t)P.ftasks.size();
+        if (P.phases.back().t1 == P.phases.back().t0) P.phases.pop_back();
+    };
+    // record one incidence of tile t of block J, with its relative indices
+    auto emit_inc = [&](int32_t J, int32_t t, const RawInc &ri) {
+        const BlockDesc &dJ = P.blk[J];
+        const BlockDesc &dK = P.blk[ri.K];
+        const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
+        const int32_t *rK = P.dsrows.data() + dK.rowoff;
+        const int32_t r0 = t * kTileRows;
+        const int32_t nr = std::min(kTileRows, dJ.r - r0);
+        Incidence in{};
+        in.valoff = dK.valoff;
+        in.mapoff = (int64_t)P.imap.size();
+        in.ld = dK.ld;
+        in.wk = (int16_t)ri.wk;
+        in.b0 = ri.b0;
+        in.a0 = ri.a0;
+        in.nI = (uint8_t)(ri.b1 - ri.b0);
+        in.nJ = (uint8_t)(ri.a1 - ri.a0);
+        // tile rows of K's rows [b0, b1): a merge along J's sorted rows
+        int32_t p = r0;
+        for (int32_t q = ri.b0; q < ri.b1; ++q) {
+            while (p < r0 + nr && rJ[p] < rK[q]) ++p;
+            P.imap.push_back((uint8_t)(p - r0));
+        }
+        for (int32_t q = ri.a0; q < ri.a1; ++q) P.imap.push_back((uint8_t)(rK[q] - dJ.col0));
+        in.cmin = (uint8_t)(rK[ri.a0] - dJ.col0);
+        in.cmax = (uint8_t)(rK[ri.a1 - 1] - dJ.col0);
+        P.incs.push_back(in);
+    };
+    std::vector<const RawInc *> small;
+    for (int32_t l = 0; l < P.nslevels; ++l) {
+        int32_t maxnb = 0;
+        open_phase(kPhaseExternal);
+        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+            const int32_t s2 = sl_list[q];
+            maxnb = std::max(maxnb, P.sbptr[s2 + 1] - P.sbptr[s2]);
+            for (int32_t J = P.sbptr[s2]; J < P.sbptr[s2 + 1]; ++J) {
+                const BlockDesc &dJ = P.blk[J];
+                const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
+                const int32_t nt = ntiles(J);
+                if ((int32_t)per_tile.size() < nt) per_tile.resize((size_t)nt);
+                for (int32_t t = 0; t < nt; ++t) per_tile[t].clear();
+                for (int64_t p = P.dptr[J]; p < P.dptr[J + 1]; ++p) {
+                    const Pair &pr = P.pairs[p];
+                    if (pr.K >= P.sbptr[s2]) break;     // internal pairs come last
+                    const int32_t ks = blk2ds[pr.K];
+                    if (pr.K != P.sbptr[ks]) continue;   // folded into the supernode's first block
+                    const int32_t kw = P.dsptr[ks + 1] - P.dsptr[ks];
+                    const BlockDesc &dK = P.blk[pr.K];
+                    const int32_t *rK = P.dsrows.data() + dK.rowoff;
+                    int32_t pos = pr.a0;
+                    while (pos < dK.r) {
+                        const int32_t li = (int32_t)(std::lower_bound(rJ, rJ + dJ.r, rK[pos]) - rJ);
+                        const int32_t t = li / kTileRows;
+                        const int32_t last = rJ[std::min((t + 1) * kTileRows, dJ.r) - 1];
+                        const int32_t end = (int32_t)(std::upper_bound(rK + pos, rK + dK.r, last) - rK);
+                        per_tile[t].push_back(RawInc{pr.K, pr.a0, pr.a1, pos, end, kw});
+                        pos = end;
+                    }
+                }
+                const bool first = J == P.sbptr[s2];
+                for (int32_t t = 0; t < nt; ++t) {
+                    const bool fuse = first && t == 0;
+                    if (per_tile[t].empty() && !fuse) continue;
+                    // large incidences first, then the rest (each keeps list order)
+                    const int32_t lim = kVariantLarge[P.svariant[s2]];
+                    auto large = [lim](const RawInc &ri) {
+                        return ri.b1 - ri.b0 >= lim && ri.a1 - ri.a0 >= lim && ri.wk >= lim;
+                    };
+                    double *ft = P.sfeat.data() + (size_t)s2 * kSuperFeatures;
+                    ft[2] += 1.0;
+                    for (const RawInc &ri : per_tile[t]) {
+                        const double fl = 2.0 * (ri.b1 - ri.b0) * (ri.a1 - ri.a0) * (double)ri.wk;
+                        const int32_t mn = std::min(std::min(ri.b1 - ri.b0, ri.a1 - ri.a0), ri.wk);
+                        ft[3] += 1.0;
+                        ft[4] += fl;
+                        if (mn >= 32) ft[5] += fl;
+                        if (mn >= 16) ft[6] += fl;
+                    }
+                    small.clear();
+                    for (const RawInc &ri : per_tile[t]) {
+                        if (large(ri)) emit_inc(J, t, ri);
+                        else small.push_back(&ri);
+                    }
+                    const int64_t big_end = (int64_t)P.incs.size();
+                    emit_wave_items(J, t, small);
+                    push_task(J, t, -1, fuse ? kFuseFactor : 0, big_end);
+                }
+            }
+        }
+        close_phase();
+        open_phase(kPhaseTrsm);
+        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+            const int32_t J = P.sbptr[sl_list[q]];
+            for (int32_t t = 1; t < ntiles(J); ++t) push_task(J, t, -1, 0, 0);
+        }
+        close_phase();
+        for (int32_t k = 1; k < maxnb; ++k) {
+            open_phase(kPhaseInternal);
+            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+                const int32_t s2 = sl_list[q];
+                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
+                if (nbs <= k) continue;
+                for (int32_t c = k; c < nbs; ++c)
+                    for (int32_t t = 0; t < ntiles(b0 + c); ++t)
+                        push_task(b0 + c, t, b0 + k - 1, (c == k && t == 0) ? kFuseFactor : 0, 0);
+            }
+            close_phase();
+            open_phase(kPhaseTrsm);
+            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+                const int32_t s2 = sl_list[q];
+                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
+                if (nbs <= k) continue;
+                for (int32_t t = 1; t < ntiles(b0 + k); ++t) push_task(b0 + k, t, -1, 0, 0);
+            }
+            close_phase();
+        }
+    }
+
+    // external phases with large incidences use the cooperative kernel
+    P.phase_coop.assign(P.phases.size(), 0);
+    for (size_t ph = 0; ph < P.phases.size(); ++ph) {
+        if (P.phases[ph].kind != kPhaseExternal) continue;
+        for (int64_t q = P.phases[ph].t0; q < P.phases[ph].t1; ++q)
+            if (P.ibig[q] > P.iptr[q]) { P.phase_coop[ph] = 1; break; }
+    }
+    // supernode features and the target supernode of every external task
+    for (int32_t s2 = 0; s2 < P.nds; ++s2) {
+        double *ft = P.sfeat.data() + (size_t)s2 * kSuperFeatures;
+        ft[0] = P.dsptr[s2 + 1] - P.dsptr[s2];
+        ft[1] = (double)(P.dsrowptr[s2 + 1] - P.dsrowptr[s2]);
+        ft[5] = ft[4] > 0 ? ft[5] / ft[4] : 0.0;
+        ft[6] = ft[4] > 0 ? ft[6] / ft[4] : 0.0;
+        ft[7] = P.slevel[s2];
+    }
+    P.task_super.assign(P.ftasks.size(), -1);
+    for (const Phase &ph : P.phases)
+        if (ph.kind == kPhaseExternal)
+            for (int64_t q = ph.t0; q < ph.t1; ++q) P.task_super[q] = blk2ds[P.ftasks[q].J];
+
+}
+
 int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
             const int32_t *user_perm, int block_width, int nd_leaf, bool relax, Plan &P)
 {
@@ -466,215 +709,8 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     //   for k = 1, 2, ...: internal updates of blocks c >= k by the now final
     //             block k-1 of the same supernode (right-looking), tile 0 of
     //             block k fused with its factorization; then block k's trsm.
-    P.sbptr.assign((size_t)P.nds + 1, 0);
-    for (int32_t s2 = 0; s2 < P.nds; ++s2) {
-        int32_t w = P.dsptr[s2 + 1] - P.dsptr[s2];
-        P.sbptr[s2 + 1] = P.sbptr[s2] + (w + B - 1) / B;
-    }
-    P.slevel.assign((size_t)P.nds, 0);
-    for (int32_t s2 = 0; s2 < P.nds; ++s2)
-        if (P.dsparent[s2] >= 0)
-            P.slevel[P.dsparent[s2]] = std::max(P.slevel[P.dsparent[s2]], P.slevel[s2] + 1);
-    P.nslevels = 0;
-    for (int32_t s2 = 0; s2 < P.nds; ++s2) P.nslevels = std::max(P.nslevels, P.slevel[s2] + 1);
-    std::vector<int32_t> sl_ptr((size_t)P.nslevels + 1, 0), sl_list((size_t)P.nds);
-    for (int32_t s2 = 0; s2 < P.nds; ++s2) sl_ptr[P.slevel[s2] + 1]++;
-    for (int32_t l = 0; l < P.nslevels; ++l) sl_ptr[l + 1] += sl_ptr[l];
-    {
-        std::vector<int32_t> fill(sl_ptr.begin(), sl_ptr.end() - 1);
-        for (int32_t s2 = 0; s2 < P.nds; ++s2) sl_list[fill[P.slevel[s2]]++] = s2;
-    }
-    auto ntiles = [&](int32_t J) { return (P.blk[J].r + kTileRows - 1) / kTileRows; };
-    P.ftasks.clear();
-    P.phases.clear();
-    P.incs.clear();
-    P.iptr.assign(1, 0);
-    std::vector<int32_t> blk2ds((size_t)P.nb);
-    for (int32_t r = 0; r < P.nds; ++r)
-        for (int32_t b = P.sbptr[r]; b < P.sbptr[r + 1]; ++b) blk2ds[b] = r;
-    // K is a block; a descendant supernode's blocks share their rows below
-    // its columns, so all of its blocks' contributions to a tile form one
-    // product whose inner dimension is the supernode's width (wk)
-    struct RawInc { int32_t K, a0, a1, b0, b1, wk; };
-    std::vector<std::vector<RawInc>> per_tile;
-    P.imap.clear();
-    P.ibig.clear();
-    P.wptr.assign(1, 0);
-    P.witems.clear();
-    P.wmap.clear();
-    // tasks without wavefront items push their (empty) ranges here
-    auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags, int64_t big_end) {
-        P.ftasks.push_back(Task{J, t, K, flags});
-        P.iptr.push_back((int64_t)P.incs.size());
-        P.ibig.push_back(big_end);
-        while ((int64_t)P.wptr.size() < 4 * (int64_t)P.ftasks.size() + 1)
-            P.wptr.push_back((int64_t)P.witems.size());
-    };
-    // tile rows of K's rows [b0, b1) and tile columns of K's rows [a0, a1)
-    std::vector<uint8_t> rrel, crel;
-    auto relative = [&](int32_t J, int32_t t, const RawInc &ri) {
-        const BlockDesc &dJ = P.blk[J];
-        const BlockDesc &dK = P.blk[ri.K];
-        const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
-        const int32_t *rK = P.dsrows.data() + dK.rowoff;
-        const int32_t r0 = t * kTileRows;
-        const int32_t nr = std::min(kTileRows, dJ.r - r0);
-        rrel.clear();
-        crel.clear();
-        int32_t p = r0;
-        for (int32_t q = ri.b0; q < ri.b1; ++q) {
-            while (p < r0 + nr && rJ[p] < rK[q]) ++p;
-            rrel.push_back((uint8_t)(p - r0));
-        }
-        for (int32_t q = ri.a0; q < ri.a1; ++q) crel.push_back((uint8_t)(rK[q] - dJ.col0));
-    };
-    // the wavefront items of one task's small incidences, wavefront-major
-    auto emit_wave_items = [&](int32_t J, int32_t t, const std::vector<const RawInc *> &small) {
-        for (int32_t v = 0; v < 4; ++v) {
-            for (const RawInc *ri : small) {
-                relative(J, t, *ri);
-                // columns are increasing: the wavefront's are a contiguous run
-                int32_t jlo = 0, jhi = 0;
-                while (jlo < (int32_t)crel.size() && crel[jlo] < 16 * v) ++jlo;
-                jhi = jlo;
-                while (jhi < (int32_t)crel.size() && crel[jhi] < 16 * v + 16) ++jhi;
-                if (jlo == jhi) continue;
-                WaveItem it{};
-                it.valoff = P.blk[ri->K].valoff;
-                it.mapoff = (int64_t)P.wmap.size();
-                it.ld = P.blk[ri->K].ld;
-                it.b0 = ri->b0;
-                it.a0 = ri->a0 + jlo;
-                it.wk = (int16_t)ri->wk;
-                it.nI = (uint8_t)rrel.size();
-                it.nJ = (uint8_t)(jhi - jlo);
-                P.wmap.insert(P.wmap.end(), rrel.begin(), rrel.end());
-                P.wmap.insert(P.wmap.end(), crel.begin() + jlo, crel.begin() + jhi);
-                P.witems.push_back(it);
-            }
-            P.wptr.push_back((int64_t)P.witems.size());
-        }
-    };
-    auto open_phase = [&](int32_t kind) { P.phases.push_back(Phase{kind, (int64_t)P.ftasks.size(), 0}); };
-    auto close_phase = [&]() {
-        P.phases.back().t1 = (int64_t)P.ftasks.size();
-        if (P.phases.back().t1 == P.phases.back().t0) P.phases.pop_back();
-    };
-    // record one incidence of tile t of block J, with its relative indices
-    auto emit_inc = [&](int32_t J, int32_t t, const RawInc &ri) {
-        const BlockDesc &dJ = P.blk[J];
-        const BlockDesc &dK = P.blk[ri.K];
-        const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
-        const int32_t *rK = P.dsrows.data() + dK.rowoff;
-        const int32_t r0 = t * kTileRows;
-        const int32_t nr = std::min(kTileRows, dJ.r - r0);
-        Incidence in{};
-        in.valoff = dK.valoff;
-        in.mapoff = (int64_t)P.imap.size();
-        in.ld = dK.ld;
-        in.wk = (int16_t)ri.wk;
-        in.b0 = ri.b0;
-        in.a0 = ri.a0;
-        in.nI = (uint8_t)(ri.b1 - ri.b0);
-        in.nJ = (uint8_t)(ri.a1 - ri.a0);
-        // tile rows of K's rows [b0, b1): a merge along J's sorted rows
-        int32_t p = r0;
-        for (int32_t q = ri.b0; q < ri.b1; ++q) {
-            while (p < r0 + nr && rJ[p] < rK[q]) ++p;
-            P.imap.push_back((uint8_t)(p - r0));
-        }
-        for (int32_t q = ri.a0; q < ri.a1; ++q) P.imap.push_back((uint8_t)(rK[q] - dJ.col0));
-        in.cmin = (uint8_t)(rK[ri.a0] - dJ.col0);
-        in.cmax = (uint8_t)(rK[ri.a1 - 1] - dJ.col0);
-        P.incs.push_back(in);
-    };
-    std::vector<const RawInc *> small;
-    for (int32_t l = 0; l < P.nslevels; ++l) {
-        int32_t maxnb = 0;
-        open_phase(kPhaseExternal);
-        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
-            const int32_t s2 = sl_list[q];
-            maxnb = std::max(maxnb, P.sbptr[s2 + 1] - P.sbptr[s2]);
-            for (int32_t J = P.sbptr[s2]; J < P.sbptr[s2 + 1]; ++J) {
-                const BlockDesc &dJ = P.blk[J];
-                const int32_t *rJ = P.dsrows.data() + dJ.rowoff;
-                const int32_t nt = ntiles(J);
-                if ((int32_t)per_tile.size() < nt) per_tile.resize((size_t)nt);
-                for (int32_t t = 0; t < nt; ++t) per_tile[t].clear();
-                for (int64_t p = P.dptr[J]; p < P.dptr[J + 1]; ++p) {
-                    const Pair &pr = P.pairs[p];
-                    if (pr.K >= P.sbptr[s2]) break;     // internal pairs come last
-                    const int32_t ks = blk2ds[pr.K];
-                    if (pr.K != P.sbptr[ks]) continue;   // folded into the supernode's first block
-                    const int32_t kw = P.dsptr[ks + 1] - P.dsptr[ks];
-                    const BlockDesc &dK = P.blk[pr.K];
-                    const int32_t *rK = P.dsrows.data() + dK.rowoff;
-                    int32_t pos = pr.a0;
-                    while (pos < dK.r) {
-                        const int32_t li = (int32_t)(std::lower_bound(rJ, rJ + dJ.r, rK[pos]) - rJ);
-                        const int32_t t = li / kTileRows;
-                        const int32_t last = rJ[std::min((t + 1) * kTileRows, dJ.r) - 1];
-                        const int32_t end = (int32_t)(std::upper_bound(rK + pos, rK + dK.r, last) - rK);
-                        per_tile[t].push_back(RawInc{pr.K, pr.a0, pr.a1, pos, end, kw});
-                        pos = end;
-                    }
-                }
-                const bool first = J == P.sbptr[s2];
-                for (int32_t t = 0; t < nt; ++t) {
-                    const bool fuse = first && t == 0;
-                    if (per_tile[t].empty() && !fuse) continue;
-                    // large incidences first, then the rest (each keeps list order)
-                    auto large = [](const RawInc &ri) {
-                        return ri.b1 - ri.b0 >= kLargeRows && ri.a1 - ri.a0 >= kLargeCols &&
-                               ri.wk >= kLargeInner;
-                    };
-                    small.clear();
-                    for (const RawInc &ri : per_tile[t]) {
-                        if (large(ri)) emit_inc(J, t, ri);
-                        else small.push_back(&ri);
-                    }
-                    const int64_t big_end = (int64_t)P.incs.size();
-                    emit_wave_items(J, t, small);
-                    push_task(J, t, -1, fuse ? kFuseFactor : 0, big_end);
-                }
-            }
-        }
-        close_phase();
-        open_phase(kPhaseTrsm);
-        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
-            const int32_t J = P.sbptr[sl_list[q]];
-            for (int32_t t = 1; t < ntiles(J); ++t) push_task(J, t, -1, 0, 0);
-        }
-        close_phase();
-        for (int32_t k = 1; k < maxnb; ++k) {
-            open_phase(kPhaseInternal);
-            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
-                const int32_t s2 = sl_list[q];
-                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
-                if (nbs <= k) continue;
-                for (int32_t c = k; c < nbs; ++c)
-                    for (int32_t t = 0; t < ntiles(b0 + c); ++t)
-                        push_task(b0 + c, t, b0 + k - 1, (c == k && t == 0) ? kFuseFactor : 0, 0);
-            }
-            close_phase();
-            open_phase(kPhaseTrsm);
-            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
-                const int32_t s2 = sl_list[q];
-                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
-                if (nbs <= k) continue;
-                for (int32_t t = 1; t < ntiles(b0 + k); ++t) push_task(b0 + k, t, -1, 0, 0);
-            }
-            close_phase();
-        }
-    }
-
-    // external phases with large incidences use the cooperative kernel
-    P.phase_coop.assign(P.phases.size(), 0);
-    for (size_t ph = 0; ph < P.phases.size(); ++ph) {
-        if (P.phases[ph].kind != kPhaseExternal) continue;
-        for (int64_t q = P.phases[ph].t0; q < P.phases[ph].t1; ++q)
-            if (P.ibig[q] > P.iptr[q]) { P.phase_coop[ph] = 1; break; }
-    }
+    P.svariant.assign((size_t)P.nds, 1);
+    build_schedule(P);
 
     // ----------------------------------- arithmetic per launch kind
     // The method's count sum_k |L_k|^2 split by the launch kind that performs

@@ -1,0 +1,124 @@
+"""GPU: the cost model's network kernels against the FP64 oracle, the
+per-supernode kernel variants against the factor oracle, and the learned
+choice of variants against exhaustive measurement (regret).
+
+Tolerances: the network runs in FP32 (u = 6e-8); outputs and gradients of
+this size (64-wide layers, 500 samples) agree with the FP64 oracle to a
+few hundred u in norm, so 1e-4 relative is the bound.  Factors under any
+variant equal the oracle to the FP64 factor bound of the parity tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_network_forward_and_gradient_match_oracle(torch_cuda):
+    torch = torch_cuda
+    from oracle import mlp as omlp
+    from paper_1705_06575_amd import costmodel as cm
+    from paper_1705_06575_amd.binding import _dev_ptr, _stream, load_library
+    L = load_library()
+    rng = np.random.default_rng(11)
+    D, n = cm.D_IN, 500
+    p = rng.normal(0.0, 0.2, omlp.param_count(D)).astype(np.float32)
+    X = rng.normal(0.0, 1.0, (n, D)).astype(np.float32)
+    t = rng.normal(0.0, 1.0, n).astype(np.float32)
+    pd, Xd, td = (torch.from_numpy(a).cuda() for a in (p, X, t))
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    assert L.sym_mlp_forward(_dev_ptr(pd, "torch.float32"), _dev_ptr(Xd, "torch.float32"), n, D,
+                             _dev_ptr(y, "torch.float32"), _stream()) == 0
+    g = torch.empty_like(pd)
+    work = torch.empty(n * (4 * 64 + 1), dtype=torch.float32, device="cuda")
+    assert L.sym_mlp_backward(_dev_ptr(pd, "torch.float32"), _dev_ptr(Xd, "torch.float32"),
+                              _dev_ptr(td, "torch.float32"), n, D, _dev_ptr(g, "torch.float32"),
+                              _dev_ptr(work, "torch.float32"), _stream()) == 0
+    y_ref = omlp.forward(p.astype(np.float64), X.astype(np.float64), D)
+    g_ref = omlp.grad(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64), D)
+    ey = np.linalg.norm(y.cpu().numpy() - y_ref) / np.linalg.norm(y_ref)
+    eg = np.linalg.norm(g.cpu().numpy() - g_ref) / np.linalg.norm(g_ref)
+    _say(f"case mlp: forward rel err {ey:.1e}, gradient rel err {eg:.1e}")
+    assert ey <= 1e-4 and eg <= 1e-4
+    # reproducible: a second backward gives the same bits
+    g2 = torch.empty_like(pd)
+    L.sym_mlp_backward(_dev_ptr(pd, "torch.float32"), _dev_ptr(Xd, "torch.float32"),
+                       _dev_ptr(td, "torch.float32"), n, D, _dev_ptr(g2, "torch.float32"),
+                       _dev_ptr(work, "torch.float32"), _stream())
+    assert torch.equal(g, g2)
+
+
+def test_training_fits_a_smooth_function(torch_cuda):
+    from paper_1705_06575_amd import costmodel as cm
+    rng = np.random.default_rng(3)
+    X = rng.normal(0.0, 1.0, (2000, cm.D_IN))
+    t = np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] + 0.1 * X[:, 3]
+    model = cm.CostModel(seed=1)
+    hist = model.fit(X, t, epochs=300, lr=3e-3)
+    _say(f"case mlp training loss {hist}")
+    assert hist[-1] < 0.1 * np.var(t)
+
+
+def test_every_variant_factors_correctly(orc, torch_cuda):
+    torch = torch_cuda
+    import paper_1705_06575_amd as S
+    w = W.knn_instance(2, nv=900)
+    f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm)
+    nds = int(an.stat("ndsuper"))
+    rng = np.random.default_rng(5)
+    Ax = torch.from_numpy(w.Ax).cuda()
+    for name, var in (("all 0", np.zeros(nds)), ("all 1", np.ones(nds)), ("all 2", np.full(nds, 2)),
+                      ("mixed", rng.integers(0, 3, nds))):
+        an.set_variants(var.astype(np.uint8))
+        assert np.array_equal(an.get("variant"), var.astype(np.uint8))
+        an.factor(Ax)
+        assert an.status() == 0
+        Lx = an.export_factor()
+        e = np.linalg.norm(Lx - f["Lx"]) / np.linalg.norm(f["Lx"])
+        _say(f"case variants {name}: rel diff {e:.1e}")
+        assert e <= 1e-13
+
+
+def test_learned_choice_beats_default_on_held_out_pattern(torch_cuda):
+    """Train on measured supernode times of two k-NN patterns, choose the
+    variants of a third: the choice's regret against the exhaustive
+    per-supernode best is no larger than that of the default variant."""
+    torch = torch_cuda
+    import paper_1705_06575_amd as S
+    from paper_1705_06575_amd import costmodel as cm
+    data = []
+    for k, nv in ((10, 6000), (11, 8000), (12, 7000)):
+        w = W.knn_instance(k, nv=nv)
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd")
+        Ax = torch.from_numpy(w.Ax).cuda()
+        T = cm.measure_variants(an, Ax)
+        data.append((an.get("super_feat"), T))
+        _say(f"case measured knn{k}: supernodes {T.shape[0]}, sum per variant {T.sum(axis=0).round(1)}, "
+             f"best {T.min(axis=1).sum():.1f}")
+    X = np.concatenate([cm.dataset(f, T)[0] for f, T in data[:2]])
+    t = np.concatenate([cm.dataset(f, T)[1] for f, T in data[:2]])
+    model = cm.CostModel(seed=2)
+    hist = model.fit(X, t, epochs=400)
+    feat, T = data[2]
+    choice = model.choose(feat)
+    r = cm.regret(T, choice)
+    _say(f"case learned choice: loss {hist[-1]:.3f} {r}, variants used {np.bincount(choice, minlength=3)}")
+    assert r["regret_us"] <= r["default_regret_us"]
