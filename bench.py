@@ -243,6 +243,67 @@ def batched(dev, steps: int = 4, reps: int = 3, tune_m: int = 4):
     return out
 
 
+def costmodel(dev, nv: int = 20000, train=(0, 1), held_out: int = 2, reps: int = 3):
+    """The learned part on the k-NN family (k = 13 union-symmetrised graphs
+    of uniform points in the unit cube, 3 dofs per vertex, random SPD 3x3
+    blocks): per-supernode variant times measured on `train` graphs train
+    the MLP; on the held-out graph its choice is compared with the default
+    variant and with the exhaustive per-supernode best -- chosen from one
+    measurement and scored on a second, independent one (summed workgroup
+    time) -- and in end-to-end factor time."""
+    import numpy as np
+    import torch
+
+    import paper_1705_06575_amd as S
+    from paper_1705_06575_amd import costmodel as cm
+    import workloads as W
+    measured = []
+    for k in train:
+        w = W.knn_instance(k, nv=nv)
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd")
+        measured.append((an.get("super_feat"),
+                         cm.measure_variants(an, torch.from_numpy(w.Ax).to(dev))))
+        an.close()
+    t0 = time.perf_counter()
+    model, min_work, hist, nrows = cm.train(measured)
+    train_s = time.perf_counter() - t0
+    w = W.knn_instance(held_out, nv=nv)
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd")
+    Ax = torch.from_numpy(w.Ax).to(dev)
+    Ta = cm.measure_variants(an, Ax)
+    Tb = cm.measure_variants(an, Ax)
+    choice = model.choose(an.get("super_feat"), min_work=min_work)
+    exhaustive = np.argmin(Ta, axis=1)
+    k = np.arange(Tb.shape[0])
+
+    def factor_ms(var):
+        an.set_variants(np.asarray(var, dtype=np.uint8))
+        an.factor(Ax)
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            e0, e1 = _events(torch)
+            e0.record()
+            an.factor(Ax)
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return round(float(np.median(out)), 3)
+
+    nds = Tb.shape[0]
+    scored = {"mlp": float(Tb[k, choice].sum()), "default": float(Tb[:, 1].sum()),
+              "exhaustive": float(Tb[k, exhaustive].sum())}
+    gain = scored["default"] - scored["exhaustive"]
+    return {"workload": f"knn13 graphs, {nv} vertices x 3 dofs (n={w.n}); train on instances {list(train)}, "
+                        f"held-out instance {held_out}",
+            "supernodes": nds, "train_rows": int(nrows), "train_loss": round(hist[-1], 4),
+            "train_s": round(train_s, 2), "variants_chosen": np.bincount(choice, minlength=3).tolist(),
+            "scored_wg_us": {kk: round(v, 1) for kk, v in scored.items()},
+            "share_of_exhaustive_gain": round((scored["default"] - scored["mlp"]) / gain, 3) if gain > 0 else None,
+            "factor_ms": {"default": factor_ms(np.ones(nds)), "mlp": factor_ms(choice),
+                          "exhaustive": factor_ms(exhaustive)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +314,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64 vs FP32+refinement comparison")
     ap.add_argument("--mixed-m", type=int, default=80, help="grid side of the mixed-precision workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched graph workload")
+    ap.add_argument("--no-costmodel", action="store_true", help="skip the learned cost model")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (byte-counter calibration)")
     ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -408,6 +470,9 @@ def main():
     if not args.no_batched:
         torch.cuda.empty_cache()
         out["batched"] = batched(dev)
+    if not args.no_costmodel:
+        torch.cuda.empty_cache()
+        out["costmodel"] = costmodel(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

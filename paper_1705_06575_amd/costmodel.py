@@ -3,14 +3,20 @@
 Each device supernode's external update can run in one of three variants
 (sym_set_variants: every incidence on the per-wavefront path, or the ones
 of at least 32 / 16 rows, columns and inner indices on the workgroup's LDS
-path).  The autotuner's measurements -- the workgroup time of every
-external-update task of a profiled factorization, summed per supernode,
-under each variant -- train a small network (the library's FP32 2 x 64
-MLP, trained on the GPU by its own forward, backward and Adam kernels) to
-predict a supernode's time from its features and a variant; the model then
-picks each supernode's variant.  Exhaustive measurement of all variants
-stays the fallback and the judge: `regret` compares a choice with the
-per-supernode best.
+path; variant 1 is the default).  The autotuner's measurements -- the
+workgroup time of every external-update task of a profiled factorization,
+summed per supernode, under each variant -- train a small network (the
+library's FP32 2 x 64 MLP, trained on the GPU by its own forward, backward
+and Adam kernels) to predict, from a supernode's features and a variant
+v != 1, log(T_v / T_1): how much faster or slower v is than the default.
+The ratio rather than the time itself is learned because the choice
+depends only on differences between variants, which are small next to
+the times.  Supernodes whose default time is below `min_us` are left out
+of training (their ratios are mostly noise and their share of the time
+negligible) and keep the default; a variant replaces the default only
+when its predicted gain exceeds `margin`.  Exhaustive measurement of all
+variants stays the fallback and the judge: `regret` compares a choice with
+the per-supernode best.
 
 Argument marshalling only: the network's arithmetic runs in the library's
 kernels (sym_mlp_forward / sym_mlp_backward / sym_mlp_adam).
@@ -69,8 +75,8 @@ def measure_variants(an, Ax, reps: int = 2) -> np.ndarray:
 
 
 class CostModel:
-    """The network plus the input/target standardization it was fit with.
-    Targets are log(time in us)."""
+    """The network plus the input standardization it was fit with.
+    Targets are log-ratios of a variant's time to the default's."""
 
     def __init__(self, seed: int = 0, device="cuda"):
         import torch
@@ -136,20 +142,46 @@ class CostModel:
                 hist.append(float(np.mean((y - np.asarray(t)) ** 2)))
         return hist
 
-    def choose(self, feat) -> np.ndarray:
-        """Variant with the smallest predicted time for every supernode."""
+    def choose(self, feat, margin: float = 0.02, min_work: float = 0.0) -> np.ndarray:
+        """Per supernode: the variant with the smallest predicted log-ratio
+        to the default, if that beats the default by more than `margin`
+        (log scale), else the default.  Supernodes with fewer than
+        `min_work` update flops keep the default."""
         f = np.asarray(feat).reshape(-1, NFEAT)
         k = f.shape[0]
-        pred = np.stack([self.predict(encode(f, np.full(k, v))) for v in range(NVAR)], axis=1)
-        return np.argmin(pred, axis=1).astype(np.uint8)
+        r = np.zeros((k, NVAR))
+        for v in (0, 2):
+            r[:, v] = self.predict(encode(f, np.full(k, v)))
+        v = np.argmin(r, axis=1)
+        keep = (r[np.arange(k), v] > -margin) | (f[:, 4] < min_work)
+        v[keep] = 1
+        return v.astype(np.uint8)
 
 
-def dataset(feat, T):
-    """Training rows (inputs, log-time targets) from measured T[s, v]."""
+def train(measured, min_us: float = 10.0, epochs: int = 400, seed: int = 0):
+    """A model fit to [(features, T), ...] measured on training patterns,
+    and the update-flop floor below which its choices keep the default
+    (the 5th percentile of the training supernodes')."""
+    X = np.concatenate([dataset(f, T, min_us)[0] for f, T in measured])
+    t = np.concatenate([dataset(f, T, min_us)[1] for f, T in measured])
+    flops = np.concatenate([np.asarray(f).reshape(-1, NFEAT)[np.asarray(T)[:, 1] >= min_us, 4]
+                            for f, T in measured])
+    model = CostModel(seed=seed)
+    hist = model.fit(X, t, epochs=epochs)
+    return model, float(np.percentile(flops, 5)), hist, X.shape[0]
+
+
+def dataset(feat, T, min_us: float = 10.0):
+    """Training rows from measured T[s, v]: inputs for variants 0 and 2 of
+    every supernode whose default time is at least min_us, targets
+    log(T[s, v] / T[s, 1])."""
     f = np.asarray(feat).reshape(-1, NFEAT)
-    k = f.shape[0]
-    X = np.concatenate([encode(f, np.full(k, v)) for v in range(NVAR)])
-    t = np.concatenate([np.log(np.maximum(T[:, v], 1e-3)) for v in range(NVAR)])
+    T = np.asarray(T)
+    sel = T[:, 1] >= min_us
+    fs = f[sel]
+    k = fs.shape[0]
+    X = np.concatenate([encode(fs, np.full(k, v)) for v in (0, 2)])
+    t = np.concatenate([np.log(np.maximum(T[sel, v], 1e-3) / T[sel, 1]) for v in (0, 2)])
     return X, t
 
 
