@@ -193,8 +193,16 @@ void build_schedule(Plan &P)
         P.incs.push_back(in);
     };
     std::vector<const RawInc *> small;
+    struct Pending {
+        int32_t J, t, s2;
+        bool fuse;
+        double cost;
+        std::vector<RawInc> incs;
+    };
+    std::vector<Pending> pending;
     for (int32_t l = 0; l < P.nslevels; ++l) {
         int32_t maxnb = 0;
+        pending.clear();
         open_phase(kPhaseExternal);
         for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
             const int32_t s2 = sl_list[q];
@@ -227,6 +235,24 @@ void build_schedule(Plan &P)
                 for (int32_t t = 0; t < nt; ++t) {
                     const bool fuse = first && t == 0;
                     if (per_tile[t].empty() && !fuse) continue;
+                    // an estimate of the tile's work: 16-wide k-batches of its
+                    // products, plus the fused factorization
+                    double cost = fuse ? 8.0 : 0.0;
+                    for (const RawInc &ri : per_tile[t]) cost += (ri.wk + 15) / 16;
+                    pending.push_back(Pending{J, t, s2, fuse, cost, per_tile[t]});
+                }
+            }
+        }
+        // longest tiles first, so that no long tile starts in the launch's
+        // last wave of workgroups (ties keep the block order)
+        std::stable_sort(pending.begin(), pending.end(),
+                         [](const Pending &a, const Pending &b) { return a.cost > b.cost; });
+        for (const Pending &pd : pending) {
+            {
+                {
+                    const int32_t J = pd.J, t = pd.t, s2 = pd.s2;
+                    const bool fuse = pd.fuse;
+                    const std::vector<RawInc> &incs_t = pd.incs;
                     // large incidences first, then the rest (each keeps list order)
                     const int32_t lim = kVariantLarge[P.svariant[s2]];
                     auto large = [lim](const RawInc &ri) {
@@ -234,7 +260,7 @@ void build_schedule(Plan &P)
                     };
                     double *ft = P.sfeat.data() + (size_t)s2 * kSuperFeatures;
                     ft[2] += 1.0;
-                    for (const RawInc &ri : per_tile[t]) {
+                    for (const RawInc &ri : incs_t) {
                         const double fl = 2.0 * (ri.b1 - ri.b0) * (ri.a1 - ri.a0) * (double)ri.wk;
                         const int32_t mn = std::min(std::min(ri.b1 - ri.b0, ri.a1 - ri.a0), ri.wk);
                         ft[3] += 1.0;
@@ -243,7 +269,7 @@ void build_schedule(Plan &P)
                         if (mn >= 16) ft[6] += fl;
                     }
                     small.clear();
-                    for (const RawInc &ri : per_tile[t]) {
+                    for (const RawInc &ri : incs_t) {
                         if (large(ri)) emit_inc(J, t, ri);
                         else small.push_back(&ri);
                     }
@@ -262,13 +288,19 @@ void build_schedule(Plan &P)
         close_phase();
         for (int32_t k = 1; k < maxnb; ++k) {
             open_phase(kPhaseInternal);
+            // the tiles fused with a factorization (the longest) lead the launch
+            for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+                const int32_t s2 = sl_list[q];
+                const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
+                if (nbs > k) push_task(b0 + k, 0, b0 + k - 1, kFuseFactor, 0);
+            }
             for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
                 const int32_t s2 = sl_list[q];
                 const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
                 if (nbs <= k) continue;
                 for (int32_t c = k; c < nbs; ++c)
-                    for (int32_t t = 0; t < ntiles(b0 + c); ++t)
-                        push_task(b0 + c, t, b0 + k - 1, (c == k && t == 0) ? kFuseFactor : 0, 0);
+                    for (int32_t t = (c == k ? 1 : 0); t < ntiles(b0 + c); ++t)
+                        push_task(b0 + c, t, b0 + k - 1, 0, 0);
             }
             close_phase();
             open_phase(kPhaseTrsm);
