@@ -100,15 +100,20 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
     return out
 
 
-FACTOR_SOURCE = os.path.join(ROOT, "paper_1705_06575_amd", "csrc", "factor.hip")
+# the factor kernels and the schedule they run (tasks, splits, items)
+FACTOR_SOURCES = [os.path.join(ROOT, "paper_1705_06575_amd", "csrc", f)
+                  for f in ("factor.hip", "symbolic.cpp", "plan.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_factor_grid3d_7pt_64.json")
 FACTOR_KERNELS = ("k_external", "k_internal", "k_trsm")
 
 
 def _source_digest() -> str:
     import hashlib
-    with open(FACTOR_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in FACTOR_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def copy_probe(nbytes: int, reps: int = 3):

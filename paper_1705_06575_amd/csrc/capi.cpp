@@ -21,6 +21,7 @@ struct sym_plan {
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
            off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
+           off_parts = 0, off_pcount = 0, off_pbuf = 0,
            off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -92,6 +93,9 @@ void layout(sym_plan *h)
     h->off_vec6 = take(sizeof(double) * (size_t)P.n);
     h->off_part = take(sizeof(double) * (sym::kDotParts + 8));
     h->off_ttime = take(sizeof(uint64_t) * P.ftasks.size());
+    h->off_parts = take(sizeof(sym::PartDesc) * P.parts.size());
+    h->off_pcount = take(sizeof(int32_t) * (size_t)P.nsplit);
+    h->off_pbuf = take((size_t)P.npartial * 4096 * elem_size(P));
     h->ws_bytes = o;
 }
 
@@ -197,6 +201,9 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.vec6 = (double *)(base + h->off_vec6);
     D.part = (double *)(base + h->off_part);
     D.ttime = (uint64_t *)(base + h->off_ttime);
+    D.parts = (sym::PartDesc *)(base + h->off_parts);
+    D.pcount = (int32_t *)(base + h->off_pcount);
+    D.pbuf = base + h->off_pbuf;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
@@ -225,6 +232,9 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.bwd_df, P.bwd_df.data(), sizeof(sym::SolveTask) * P.bwd_df.size(), s);
     if (e == hipSuccess && !P.ftasks.empty())
         e = hipMemsetAsync(D.ttime, 0, sizeof(uint64_t) * P.ftasks.size(), s);
+    if (e == hipSuccess) e = upload(D.parts, P.parts.data(), sizeof(sym::PartDesc) * P.parts.size(), s);
+    if (e == hipSuccess && P.nsplit > 0)
+        e = hipMemsetAsync(D.pcount, 0, sizeof(int32_t) * (size_t)P.nsplit, s);
     if (e == hipSuccess) e = upload(D.arowptr, P.arowptr.data(), sizeof(int64_t) * P.arowptr.size(), s);
     if (e == hipSuccess) e = upload(D.acol, P.acol.data(), sizeof(int32_t) * P.acol.size(), s);
     if (e == hipSuccess) e = upload(D.aval, P.aval.data(), sizeof(int64_t) * P.aval.size(), s);
@@ -759,7 +769,7 @@ struct sym_batch {
     sym_plan *h = nullptr;
     int32_t m = 0;
     size_t ws_bytes = 0, off_Lx = 0, off_vec = 0, off_vec2 = 0, off_vec3 = 0, off_info = 0,
-           off_red = 0, off_sync = 0;
+           off_red = 0, off_sync = 0, off_pcount = 0, off_pbuf = 0;
     sym::DevicePlan D;              // the analysis's plan arrays, the batch's own buffers
     bool bound = false, factored = false;
     hipStream_t stream = nullptr;
@@ -784,6 +794,8 @@ int sym_batch_create(sym_handle h, int32_t m, sym_batch_t *out)
     b->off_info = take(M * sizeof(int32_t) * 4);
     b->off_red = take(M * sizeof(double) * 4);
     b->off_sync = take(M * sizeof(int32_t) * (2 * (size_t)P.nb + 16));
+    b->off_pcount = take(M * sizeof(int32_t) * (size_t)P.nsplit);
+    b->off_pbuf = take(M * (size_t)P.npartial * 4096 * elem_size(P));
     b->ws_bytes = std::max<size_t>(o, 256);
     *out = b;
     return SYM_OK;
@@ -814,9 +826,16 @@ int sym_batch_bind(sym_batch_t b, void *dev_ws, size_t bytes, void *stream)
     D.pend = (int32_t *)(base + b->off_sync);
     D.done = D.pend + (size_t)b->m * P.nb;
     D.ticket = D.done + (size_t)b->m * P.nb;
+    D.pcount = (int32_t *)(base + b->off_pcount);
+    D.pbuf = base + b->off_pbuf;
     // single-instance scratch of the analysis is not used by batches
     D.vec4 = D.vec5 = D.vec6 = D.part = nullptr;
+    D.ttime = nullptr;
     b->D = D;
+    if (P.nsplit > 0 &&
+        hipMemsetAsync(D.pcount, 0, sizeof(int32_t) * (size_t)P.nsplit * (size_t)b->m,
+                       (hipStream_t)stream) != hipSuccess)
+        return SYM_EHIP;
     b->stream = (hipStream_t)stream;
     b->bound = true;
     b->factored = false;

@@ -46,6 +46,9 @@ struct DevicePlan {
     double *vec6 = nullptr;         // n scratch: preconditioned residual z
     double *part = nullptr;         // kDotParts partial sums of a dot product
     uint64_t *ttime = nullptr;      // tasks: duration of each profiled external task (100 MHz ticks)
+    PartDesc *parts = nullptr;      // split external tiles' parts
+    int32_t *pcount = nullptr;      // nsplit arrival counters (per instance)
+    void *pbuf = nullptr;           // npartial 64 x 64 partial tiles, T (per instance)
     // dataflow sweeps
     int64_t *chunk_tptr = nullptr;  // fwd tasks+1
     int32_t *chunk_tgt = nullptr;   // target blocks of each chunk

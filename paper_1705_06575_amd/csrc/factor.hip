@@ -27,7 +27,11 @@
 //                its product with block k-1 (matrix cores, accumulators
 //                seeded with the tile); tile 0 of block k then factors it.
 // Every tile has exactly one writer per launch and a fixed summation order,
-// so results are bitwise reproducible.
+// so results are bitwise reproducible.  A long external tile is split into
+// parts that run as separate workgroups of the same launch: each stores its
+// partial sum with device-coherent stores and counts its arrival with a
+// device-scope atomic; the last part adds the partial sums in part order
+// and finishes the tile (no workgroup waits for another).
 // A non-positive (or NaN) pivot stores the smallest failing column in a
 // device word; the factorization continues (results are then undefined).
 // A second word records the first block whose descendant rows do not nest
@@ -753,15 +757,21 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
                                                  const BlockDesc *__restrict__ blk,
                                                  T *__restrict__ Lx, int32_t *__restrict__ info,
                                                  int64_t lx_stride,
-                                                 unsigned long long *__restrict__ ttime)
+                                                 unsigned long long *__restrict__ ttime,
+                                                 const PartDesc *__restrict__ parts,
+                                                 int32_t *pcount, T *pbuf, int32_t nsplit,
+                                                 int64_t npartial)
 {
     const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
     __shared__ T C[64 * LDC];
     __shared__ T As[COOP ? 2 : 1][16][64];
     Lx += blockIdx.y * lx_stride;
     info += 4 * blockIdx.y;
+    pcount += (int64_t)blockIdx.y * nsplit;
+    pbuf += (int64_t)blockIdx.y * npartial * 4096;
     __shared__ T Bs[COOP ? 2 : 1][16][64];
     __shared__ int32_t s_rel[COOP ? 128 : 1];
+    __shared__ int s_last;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -772,8 +782,14 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
     const int nr = min(TR, J.r - r0);
     const int w = J.w;
     T *LJ = Lx + J.valoff;
+    const bool partial = (tk.flags & kPartial) != 0;
 
-    tile_in(C, LJ + r0, J.ld, nr, w);
+    // a part of a split tile accumulates from zero; other tiles from their values
+    if (partial) {
+        for (int k = tid; k < 64 * LDC; k += NT) C[k] = T(0);
+    } else {
+        tile_in(C, LJ + r0, J.ld, nr, w);
+    }
     __syncthreads();
 
     int64_t q = iptr[blockIdx.x];
@@ -795,9 +811,60 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
     if (i0 < i1) wave_items(C, witems, wmap, (const T *)Lx, i0, i1, r0, nr, w);
     __syncthreads();
 
-    if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
-
-    tile_out(LJ + r0, C, J.ld, nr, w);
+    bool finish = !partial;
+    if (partial) {
+        // store this part's sum (written through to the device-coherent
+        // level), count arrivals; the last part adds every part's sum, in
+        // part order, to the tile and finishes it
+        const PartDesc pd = parts[tk.K];
+        T *slot = pbuf + (int64_t)(pd.slot0 + pd.part) * 4096;
+        for (int k = tid; k < 4096; k += NT) {
+            const int c = k >> 6, r = k & 63;
+            if (r < nr && c < w)
+                __hip_atomic_store(slot + k, C[c * LDC + r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(&pcount[pd.counter], 1) == pd.nparts - 1;
+        __syncthreads();
+        if (s_last) {
+            tile_in(C, LJ + r0, J.ld, nr, w);
+            __syncthreads();
+            // each thread owns 16 fixed entries; per part its 16 loads are
+            // issued together (slot entries outside the tile are loaded but
+            // never used, so the loads stay unconditional and in bounds)
+            constexpr int E = 4096 / NT;
+            const T *base = pbuf + (int64_t)pd.slot0 * 4096 + tid;
+            T acc[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = tid + e * NT;
+                acc[e] = C[(k >> 6) * LDC + (k & 63)];
+            }
+            for (int p = 0; p < pd.nparts; ++p) {
+                T v[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    v[e] = __hip_atomic_load(base + (int64_t)p * 4096 + e * NT, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] += v[e];
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = tid + e * NT;
+                if ((k & 63) < nr && (k >> 6) < w) C[(k >> 6) * LDC + (k & 63)] = acc[e];
+            }
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(&pcount[pd.counter], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            finish = true;
+        }
+    }
+    if (finish) {
+        if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
+        tile_out(LJ + r0, C, J.ld, nr, w);
+    }
     if (ttime && blockIdx.y == 0) {
         __syncthreads();                    // every wavefront's work is issued
         if (threadIdx.x == 0) ttime[blockIdx.x] = wall_clock64() - t_start;
@@ -969,11 +1036,13 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
             k_external<T, true><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                  D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                 D.wmap, D.blk, Lx, D.info, lxs, ttime(ph));
+                                                 D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
+                                                 D.pcount, (T *)D.pbuf, P.nsplit, P.npartial);
         else if (ph.kind == kPhaseExternal)
             k_external<T, false><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                   D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                  D.wmap, D.blk, Lx, D.info, lxs, ttime(ph));
+                                                  D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
+                                                  D.pcount, (T *)D.pbuf, P.nsplit, P.npartial);
         else if (ph.kind == kPhaseInternal)
             k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs);
         else

@@ -38,7 +38,7 @@ struct Pair {           // 16 bytes: descendant block K updates target block J
 struct Task {           // 16 bytes: one row tile of one block
     int32_t J;          // target block
     int32_t t;          // tile index: local rows [t*T, min((t+1)*T, r_J))
-    int32_t K;          // source block (internal updates), -1 otherwise
+    int32_t K;          // source block (internal updates), PartDesc index (kPartial), else -1
     int32_t flags;      // kFuseFactor: the task also factors the block
 };
 
@@ -80,6 +80,21 @@ static_assert(sizeof(WaveItem) == 32, "WaveItem layout is shared with the device
 static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
 constexpr int32_t kFuseFactor = 1;
+// A long external-update tile is split into parts (tasks of the same launch
+// with kPartial and K = index of their PartDesc): each part accumulates
+// its share of the products into a partial tile; the part that finishes
+// last adds all partials in part order to the tile (and factors it if the
+// tile carries kFuseFactor).
+constexpr int32_t kPartial = 2;
+constexpr double kSplitUnits = 96.0;   // a tile's estimated 16-wide k-batches per part
+
+struct PartDesc {       // 16 bytes, device-visible
+    int32_t counter;    // arrival counter of the split tile (zero between launches)
+    int32_t part;       // this part's index
+    int32_t nparts;
+    int32_t slot0;      // partial-tile slot of part 0 (part p uses slot0 + p)
+};
+static_assert(sizeof(PartDesc) == 16, "PartDesc layout is shared with the device");
 
 // Kernel variant of a target supernode's external update: an incidence is
 // "large" -- multiplied by the whole workgroup through LDS -- when its
@@ -162,6 +177,12 @@ struct Plan {
     std::vector<int32_t> fwd_pend;      // nb: forward chunks whose rows meet the block
     std::vector<int32_t> bwd_pend;      // nb: off-diagonal chunks of the block
     std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers, then diagonals
+
+    // split external tiles: part descriptors, and the counts of arrival
+    // counters and of 64 x 64 partial-tile slots they use
+    std::vector<PartDesc> parts;
+    int32_t nsplit = 0;
+    int64_t npartial = 0;
 
     // per device supernode: kernel variant of its external update, and the
     // features a cost model sees (kSuperFeatures each): width, rows, row

@@ -4,6 +4,7 @@
 // column blocks, level sets, descendant lists (the prune set of the update
 // phase) and the map from A's entries into L's panels.
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <climits>
 #include <cstring>
@@ -68,6 +69,9 @@ void permute_lower(int32_t n, const int64_t *Ap, const int32_t *Ai,
 void build_schedule(Plan &P)
 {
     const int32_t B = P.B;
+    P.parts.clear();
+    P.nsplit = 0;
+    P.npartial = 0;
     if ((int32_t)P.svariant.size() != P.nds) P.svariant.assign((size_t)P.nds, 1);
     P.sfeat.assign((size_t)P.nds * kSuperFeatures, 0.0);
     P.sbptr.assign((size_t)P.nds + 1, 0);
@@ -247,19 +251,43 @@ void build_schedule(Plan &P)
         // last wave of workgroups (ties keep the block order)
         std::stable_sort(pending.begin(), pending.end(),
                          [](const Pending &a, const Pending &b) { return a.cost > b.cost; });
+        // a long tile becomes parts of about kSplitUnits each, contiguous
+        // in its incidence list; counters and partial-sum slots are per
+        // launch, so every level reuses them from the start
+        int32_t lv_counters = 0;
+        int64_t lv_slots = 0;
         for (const Pending &pd : pending) {
-            {
-                {
+            int32_t np = 1;
+            if (pd.cost > kSplitUnits)
+                np = std::min<int32_t>((int32_t)std::ceil(pd.cost / kSplitUnits), (int32_t)pd.incs.size());
+            std::vector<size_t> cut(1, 0);
+            if (np > 1) {
+                double acc = 0.0;
+                const double share = pd.cost / np;
+                for (size_t i = 0; i < pd.incs.size() && (int32_t)cut.size() < np; ++i) {
+                    acc += (pd.incs[i].wk + 15) / 16;
+                    if (acc >= share * (double)cut.size() && i + 1 < pd.incs.size()) cut.push_back(i + 1);
+                }
+                np = (int32_t)cut.size();
+            }
+            cut.push_back(pd.incs.size());
+            const int32_t counter = np > 1 ? lv_counters++ : -1;
+            const int64_t slot0 = lv_slots;
+            if (np > 1) lv_slots += np;
+            P.nsplit = std::max(P.nsplit, lv_counters);
+            P.npartial = std::max(P.npartial, lv_slots);
+            for (int32_t part = 0; part < np; ++part) {
                     const int32_t J = pd.J, t = pd.t, s2 = pd.s2;
                     const bool fuse = pd.fuse;
-                    const std::vector<RawInc> &incs_t = pd.incs;
+                    const std::vector<RawInc> incs_t(pd.incs.begin() + (ptrdiff_t)cut[part],
+                                                     pd.incs.begin() + (ptrdiff_t)cut[part + 1]);
                     // large incidences first, then the rest (each keeps list order)
                     const int32_t lim = kVariantLarge[P.svariant[s2]];
                     auto large = [lim](const RawInc &ri) {
                         return ri.b1 - ri.b0 >= lim && ri.a1 - ri.a0 >= lim && ri.wk >= lim;
                     };
                     double *ft = P.sfeat.data() + (size_t)s2 * kSuperFeatures;
-                    ft[2] += 1.0;
+                    if (part == 0) ft[2] += 1.0;
                     for (const RawInc &ri : incs_t) {
                         const double fl = 2.0 * (ri.b1 - ri.b0) * (ri.a1 - ri.a0) * (double)ri.wk;
                         const int32_t mn = std::min(std::min(ri.b1 - ri.b0, ri.a1 - ri.a0), ri.wk);
@@ -275,8 +303,13 @@ void build_schedule(Plan &P)
                     }
                     const int64_t big_end = (int64_t)P.incs.size();
                     emit_wave_items(J, t, small);
-                    push_task(J, t, -1, fuse ? kFuseFactor : 0, big_end);
-                }
+                    if (np > 1) {
+                        P.parts.push_back(PartDesc{counter, part, np, (int32_t)slot0});
+                        push_task(J, t, (int32_t)P.parts.size() - 1,
+                                  (fuse ? kFuseFactor : 0) | kPartial, big_end);
+                    } else {
+                        push_task(J, t, -1, fuse ? kFuseFactor : 0, big_end);
+                    }
             }
         }
         close_phase();
