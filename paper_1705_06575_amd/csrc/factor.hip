@@ -307,12 +307,13 @@ __device__ __forceinline__ float pivot_rsqrt(float d)
 
 // One wavefront factors the 16-column sub-panel C[c0 : nr, c0 : c0 + wb]
 // (LDS, column-major, stride LDC) in place: lane i holds row c0 + i in
-// registers.  Column k: the pivot's reciprocal square root r (the diagonal
-// entry is d r), the scaling of the rows below it by r, and the rank-1 update of the sub-panel's later
-// columns, with the needed entries of other rows read across lanes (no
+// registers.  Column k: the pivot's reciprocal square root r scales the
+// whole column (the diagonal entry d becomes d r), then the later columns
+// take the rank-1 update with the multipliers read across lanes (no
 // barriers).  Rows c0 .. c0 + wb - 1 form the diagonal block (Cholesky);
-// the rows below get the triangular solve against it.  All 16 columns run
-// without branches; columns past wb start at zero, never feed the real ones
+// the rows below get the triangular solve against it.  No lane masks: the
+// entries above the diagonal receive harmless updates (they are stored and
+// never read).  Columns past wb start at zero, never feed the real ones
 // (only later columns depend on a column) and are not stored.
 template <typename T>
 __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
@@ -327,21 +328,16 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
     double r[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? (double)C[(c0 + c) * LDC + row] : 0.0;
+    int bad = INT_MAX;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const double d = lane_value(r[k], k);
-        if (k < wb && !(d > 0.0) && lane == 0) atomicMin(info, col0 + c0 + k);
-        const double inv = pivot_rsqrt(d);
-        r[k] = lane == k ? d * inv : (lane > k ? r[k] * inv : r[k]);
+        bad = (k < wb && !(d > 0.0)) ? min(bad, col0 + c0 + k) : bad;
+        r[k] *= pivot_rsqrt(d);
 #pragma unroll
-        for (int c = k + 1; c < 16; ++c) {
-            const double lck = lane_value(r[k], c);
-            r[c] = lane >= c ? r[c] - r[k] * lck : r[c];
-        }
-        // columns form a dependence chain anyway; keeping each column's
-        // cross-lane reads together bounds the scalar registers they use
-        __builtin_amdgcn_sched_barrier(0);
+        for (int c = k + 1; c < 16; ++c) r[c] = fma(-r[k], lane_value(r[k], c), r[c]);
     }
+    if (bad != INT_MAX && lane == 0) atomicMin(info, bad);
 #pragma unroll
     for (int c = 0; c < 16; ++c)
         if (mine && c < wb) C[(c0 + c) * LDC + row] = (T)r[c];
@@ -427,13 +423,16 @@ __device__ __forceinline__ void wave_rows_solve(T *X, const T *D, const T *M, in
 // never-read storage; a diag_off of 64 or more disables the skipping.
 template <typename T>
 __device__ __forceinline__ void block_update(T *C, const T *X, const T *Y, int ra, int nr,
-                                             int ca, int w, int k0, int kw, int diag_off)
+                                             int ca, int w, int k0, int kw, int diag_off,
+                                             int wave0 = 0)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nrb = (nr - ra + 15) >> 4;
     const int ncb = (w - ca + 15) >> 4;
-    for (int blk = wave; blk < nrb * ncb; blk += NT / 64) {
+    // blocks are shared by the wavefronts wave0 .. NT / 64 - 1
+    if (wave < wave0) return;
+    for (int blk = wave - wave0; blk < nrb * ncb; blk += NT / 64 - wave0) {
         const int rb = ra + 16 * (blk % nrb);
         const int cb = ca + 16 * (blk / nrb);
         if (rb + 15 + diag_off < cb) continue;
@@ -459,20 +458,27 @@ __device__ __forceinline__ void block_update(T *C, const T *X, const T *Y, int r
 
 // Cholesky of an nr x w panel (nr, w <= 64) held column-major in LDS:
 // rows [0, w) are the diagonal block, rows [w, nr) the rows below it (their
-// triangular solve is part of the same sweep).  Blocked by 16 columns: one
-// wavefront factors a sub-panel, then all four update the columns to its
-// right with matrix-core products.  Called by all threads of the workgroup.
+// triangular solve is part of the same sweep).  Blocked by 16 columns with
+// look-ahead: once sub-panel j is factored, all four wavefronts apply its
+// update to sub-panel j + 1's columns; then wavefront 0 factors sub-panel
+// j + 1 while wavefronts 1..3 apply sub-panel j's update to the columns
+// beyond it (matrix-core products).  Every column still receives the
+// sub-panels' updates in order.  Called by all threads of the workgroup.
 template <typename T>
 __device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info)
 {
-    for (int c0 = 0; c0 < w; c0 += 16) {
+    const int wave = threadIdx.x >> 6;
+    if (wave == 0) wave_subpanel(C, 0, min(16, w), nr, col0, info);
+    __syncthreads();
+    for (int c0 = 16; c0 < w; c0 += 16) {
         const int wb = min(16, w - c0);
-        if ((threadIdx.x >> 6) == 0) wave_subpanel(C, c0, wb, nr, col0, info);
+        block_update(C, C, C, c0, nr, c0, c0 + wb, c0 - 16, 16, 0);
         __syncthreads();
-        if (c0 + wb < w) {
-            block_update(C, C, C, c0 + wb, nr, c0 + wb, w, c0, wb, 0);
-            __syncthreads();
-        }
+        if (wave == 0)
+            wave_subpanel(C, c0, wb, nr, col0, info);
+        else if (c0 + wb < w)
+            block_update(C, C, C, c0 + wb, nr, c0 + wb, w, c0 - 16, 16, 0, 1);
+        __syncthreads();
     }
 }
 
