@@ -187,62 +187,24 @@ template <> struct Mfma<float> {
     __device__ static __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// acc[m][n] += sgn * A[rows, :] * B[cols, :]^T for the 32 x 32 quadrant
-// (wr, wc) of a product with nI x nJ valid entries and inner dimension wk.
-// A and B are column-major panels with leading dimension ld; rows and
-// columns of the quadrant are 32*wr + 16*m + (lane % 16) and
-// 32*wc + 16*n + (lane % 16).  Entries outside the valid range read as 0.
+// acc[m][n] -= A[rows, 0:wk] * B[cols, 0:wk]^T for the 32 x 32 quadrant
+// (wr, wc), inner dimension wk of any length: the operands stream in chunks
+// of 16 inner indices through two register stages (the next chunk is in
+// flight while the current one is multiplied).  Loads are unconditional
+// (addresses clamped into the valid rows, columns and inner range), so
+// every chunk issues the same 16 loads and each product waits for its own
+// chunk only; the inner range is masked at the product.
 template <typename T>
-__device__ __forceinline__ void wave_product(const T *__restrict__ pa, const T *__restrict__ pb,
-                                             int64_t ld, int nI, int nJ, int wk, int wr, int wc,
-                                             T sgn, typename Mfma<T>::acc_t (&acc)[2][2])
+struct Chunk16 {
+    T a0[4], a1[4], b0[4], b1[4];
+};
+template <typename T>
+__device__ __forceinline__ void wave_product_pipe(const T *__restrict__ pa, const T *__restrict__ pb,
+                                                  int64_t ld, int nI, int nJ, int wk, int wr, int wc,
+                                                  typename Mfma<T>::acc_t (&acc)[2][2])
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int ra0 = 32 * wr + li, ra1 = ra0 + 16;
-    const int cb0 = 32 * wc + li, cb1 = cb0 + 16;
-    const bool va0 = ra0 < nI, va1 = ra1 < nI, vb0 = cb0 < nJ, vb1 = cb1 < nJ;
-    // operands of eight k-steps (32 inner indices) are loaded together
-    for (int k0 = 0; k0 < wk; k0 += 32) {
-        T a0[8], a1[8], b0[8], b1[8];
-#pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const int k = k0 + 4 * st + lk;
-            const bool vk = k < wk;
-            const int64_t ko = vk ? (int64_t)k * ld : 0;
-            const T x0 = pa[(va0 ? ra0 : 0) + ko], x1 = pa[(va1 ? ra1 : 0) + ko];
-            const T y0 = pb[(vb0 ? cb0 : 0) + ko], y1 = pb[(vb1 ? cb1 : 0) + ko];
-            a0[st] = (va0 && vk) ? sgn * x0 : T(0);
-            a1[st] = (va1 && vk) ? sgn * x1 : T(0);
-            b0[st] = (vb0 && vk) ? y0 : T(0);
-            b1[st] = (vb1 && vk) ? y1 : T(0);
-        }
-#pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            if (k0 + 4 * st < wk) {
-                acc[0][0] = Mfma<T>::mma(a0[st], b0[st], acc[0][0]);
-                acc[0][1] = Mfma<T>::mma(a0[st], b1[st], acc[0][1]);
-                acc[1][0] = Mfma<T>::mma(a1[st], b0[st], acc[1][0]);
-                acc[1][1] = Mfma<T>::mma(a1[st], b1[st], acc[1][1]);
-            }
-        }
-    }
-}
-
-// acc[m][n] -= A[rows, :] * B[cols, :]^T for the 32 x 32 quadrant (wr, wc)
-// of a product with inner dimension wk <= 64, rows and columns as in
-// wave_product.  All operand loads are issued before the first product
-// (addresses clamped into the valid range, invalid k masked at the
-// product), so the whole update costs one memory latency.
-template <typename T>
-__device__ __forceinline__ void wave_product_all(const T *__restrict__ pa, const T *__restrict__ pb,
-                                                 int64_t ld, int nI, int nJ, int wk, int wr, int wc,
-                                                 typename Mfma<T>::acc_t (&acc)[2][2])
-{
-    const int lane = threadIdx.x & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    // 32-bit byte offsets from the uniform panel pointers (a panel is far
-    // below 4 GiB), so the loads take the scalar-base addressing form
     const uint32_t ra0 = sizeof(T) * min(32 * wr + li, nI - 1);
     const uint32_t ra1 = sizeof(T) * min(32 * wr + 16 + li, nI - 1);
     const uint32_t cb0 = sizeof(T) * min(32 * wc + li, nJ - 1);
@@ -250,26 +212,40 @@ __device__ __forceinline__ void wave_product_all(const T *__restrict__ pa, const
     const uint32_t ldb = sizeof(T) * (uint32_t)ld;
     const char *ca = reinterpret_cast<const char *>(pa);
     const char *cbp = reinterpret_cast<const char *>(pb);
-    T a0[16], a1[16], b0[16], b1[16];
+    auto load = [&](Chunk16<T> &x, int kc) {
 #pragma unroll
-    for (int st = 0; st < 16; ++st) {
-        const uint32_t ko = (uint32_t)min(4 * st + lk, wk - 1) * ldb;
-        a0[st] = *reinterpret_cast<const T *>(ca + (ra0 + ko));
-        a1[st] = *reinterpret_cast<const T *>(ca + (ra1 + ko));
-        b0[st] = *reinterpret_cast<const T *>(cbp + (cb0 + ko));
-        b1[st] = *reinterpret_cast<const T *>(cbp + (cb1 + ko));
-    }
-#pragma unroll
-    for (int st = 0; st < 16; ++st) {
-        if (4 * st < wk) {
-            const bool vk = 4 * st + lk < wk;
-            const T x0 = vk ? -a0[st] : T(0), x1 = vk ? -a1[st] : T(0);
-            acc[0][0] = Mfma<T>::mma(x0, b0[st], acc[0][0]);
-            acc[0][1] = Mfma<T>::mma(x0, b1[st], acc[0][1]);
-            acc[1][0] = Mfma<T>::mma(x1, b0[st], acc[1][0]);
-            acc[1][1] = Mfma<T>::mma(x1, b1[st], acc[1][1]);
+        for (int st = 0; st < 4; ++st) {
+            const uint32_t ko = (uint32_t)min(kc + 4 * st + lk, wk - 1) * ldb;
+            x.a0[st] = *reinterpret_cast<const T *>(ca + (ra0 + ko));
+            x.a1[st] = *reinterpret_cast<const T *>(ca + (ra1 + ko));
+            x.b0[st] = *reinterpret_cast<const T *>(cbp + (cb0 + ko));
+            x.b1[st] = *reinterpret_cast<const T *>(cbp + (cb1 + ko));
         }
+    };
+    auto compute = [&](const Chunk16<T> &x, int kc) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const bool vk = kc + 4 * st + lk < wk;
+            const T x0 = vk ? -x.a0[st] : T(0), x1 = vk ? -x.a1[st] : T(0);
+            acc[0][0] = Mfma<T>::mma(x0, x.b0[st], acc[0][0]);
+            acc[0][1] = Mfma<T>::mma(x0, x.b1[st], acc[0][1]);
+            acc[1][0] = Mfma<T>::mma(x1, x.b0[st], acc[1][0]);
+            acc[1][1] = Mfma<T>::mma(x1, x.b1[st], acc[1][1]);
+        }
+    };
+    // an even number of chunks (at least two); the last pair has no loads
+    const int nq = max(2, ((wk + 31) >> 5) << 1);
+    Chunk16<T> s0, s1;
+    load(s0, 0);
+    load(s1, 16);
+    for (int q = 0; q < nq - 2; q += 2) {
+        compute(s0, 16 * q);
+        load(s0, 16 * (q + 2));
+        compute(s1, 16 * (q + 1));
+        load(s1, 16 * (q + 3));
     }
+    compute(s0, 16 * (nq - 2));
+    compute(s1, 16 * (nq - 1));
 }
 
 // Value of v in lane `src` (a compile-time or wave-uniform lane index).
@@ -883,7 +859,7 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
 // are needed.  The accumulators start from the tile's current values.  With
 // kFuseFactor (tile 0 of block K+1) the result is factored in LDS.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
+__global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tasks,
                                                  const BlockDesc *__restrict__ blk,
                                                  T *__restrict__ Lx, int32_t *__restrict__ info,
                                                  int64_t lx_stride)
@@ -925,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_internal(const Task *__restrict__ tasks,
                     const T val = *reinterpret_cast<const T *>(tb + off);
                     acc[m][n][v] = ok ? val : T(0);
                 }
-        wave_product_all<T>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
+        wave_product_pipe<T>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
     }
     if (tk.flags & kFuseFactor) {
         if (active) {
