@@ -471,19 +471,20 @@ __device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int3
 // ahead.  With kFuseFactor the tile is tile 0 of a supernode's first block,
 // which is then factored in place.
 // Large incidences of one tile, by the whole workgroup: the product's
-// inner dimension is walked in chunks of 16 staged through double-buffered
+// inner dimension is walked in chunks of KC staged through double-buffered
 // LDS, each thread keeping the loads of the next two chunks in flight in
 // registers; wavefront (wr, wc) owns the 32 x 32 quadrant (wr, wc) of the
 // 64 x 64 product and subtracts it at the relative positions.  One barrier
-// per chunk.
-template <typename T>
-__device__ __forceinline__ void load_chunk(T (&va)[4], T (&vb)[4], const T *__restrict__ LK,
+// per chunk.  With KC = 8 the staging buffers are small enough for three
+// workgroups per CU.
+template <typename T, int KC>
+__device__ __forceinline__ void load_chunk(T (&va)[KC / 4], T (&vb)[KC / 4], const T *__restrict__ LK,
                                            const Incidence &in, int kc)
 {
     const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;
     const int64_t ld = in.ld;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < KC / 4; ++j) {
         const int k = kc + kq + 4 * j;
         const bool vk = k < in.wk;
         const int64_t ko = vk ? (int64_t)k * ld : 0;
@@ -495,11 +496,12 @@ __device__ __forceinline__ void load_chunk(T (&va)[4], T (&vb)[4], const T *__re
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void coop_product(T *C, T (*As)[16][64], T (*Bs)[16][64], int32_t *s_rel,
+template <typename T, int KC>
+__device__ __forceinline__ void coop_product(T *C, T (*As)[KC][64], T (*Bs)[KC][64], int32_t *s_rel,
                                              const Incidence &in, const uint8_t *__restrict__ imap,
                                              const T *__restrict__ Lx, int r0, int nr, int w)
 {
+    constexpr int J4 = KC / 4;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
@@ -509,34 +511,37 @@ __device__ __forceinline__ void coop_product(T *C, T (*As)[16][64], T (*Bs)[16][
     const uint8_t *mp = imap + in.mapoff;
     if (tid < 64) s_rel[tid] = tid < nI ? (int)mp[tid] : 0;
     else if (tid < 128) s_rel[tid] = tid - 64 < nJ ? (int)mp[nI + tid - 64] : 0;
-    const int nch = (in.wk + 15) >> 4;
-    T pa[2][4], pb[2][4];
-    load_chunk(pa[0], pb[0], LK, in, 0);
-    if (nch > 1) load_chunk(pa[1], pb[1], LK, in, 16);
+    const int nch = (in.wk + KC - 1) / KC;
+    T pa[2][J4], pb[2][J4];
+    load_chunk<T, KC>(pa[0], pb[0], LK, in, 0);
+    if (nch > 1) load_chunk<T, KC>(pa[1], pb[1], LK, in, KC);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < J4; ++j) {
         As[0][kq + 4 * j][r] = pa[0][j];
         Bs[0][kq + 4 * j][r] = pb[0][j];
     }
-    if (nch > 2) load_chunk(pa[0], pb[0], LK, in, 32);
+    if (nch > 2) load_chunk<T, KC>(pa[0], pb[0], LK, in, 2 * KC);
     __syncthreads();
     const bool active = 32 * wr < nI && 32 * wc < nJ;
+    // 16-row and 16-column blocks of the quadrant past the product's extent
+    // are skipped (wave-uniform conditions)
+    const bool a1v = 32 * wr + 16 < nI, b1v = 32 * wc + 16 < nJ;
     typename Mfma<T>::acc_t acc[2][2] = {};
     const int li = lane & 15;
     for (int c = 0; c < nch; ++c) {
         const int buf = c & 1;
         if (active) {
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
+            for (int st = 0; st < KC / 4; ++st) {
                 const int kl = 4 * st + (lane >> 4);
                 const T a0 = As[buf][kl][32 * wr + li];
                 const T a1 = As[buf][kl][32 * wr + 16 + li];
                 const T b0 = Bs[buf][kl][32 * wc + li];
                 const T b1 = Bs[buf][kl][32 * wc + 16 + li];
                 acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
-                acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
-                acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
-                acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+                if (b1v) acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
+                if (a1v) acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
+                if (a1v && b1v) acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
             }
         }
         if (c + 1 < nch) {
@@ -544,11 +549,11 @@ __device__ __forceinline__ void coop_product(T *C, T (*As)[16][64], T (*Bs)[16][
             // read in iteration c-1, before the previous barrier
             const int rs = (c + 1) & 1;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < J4; ++j) {
                 As[buf ^ 1][kq + 4 * j][r] = pa[rs][j];
                 Bs[buf ^ 1][kq + 4 * j][r] = pb[rs][j];
             }
-            if (c + 3 < nch) load_chunk(pa[rs], pb[rs], LK, in, 16 * (c + 3));
+            if (c + 3 < nch) load_chunk<T, KC>(pa[rs], pb[rs], LK, in, KC * (c + 3));
         }
         __syncthreads();
     }
@@ -728,7 +733,7 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
 }
 
 template <typename T, bool COOP>
-__global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__restrict__ tasks,
+__global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tasks,
                                                  const int64_t *__restrict__ iptr,
                                                  const int64_t *__restrict__ ibig,
                                                  const Incidence *__restrict__ incs,
@@ -746,12 +751,13 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
 {
     const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
     __shared__ T C[64 * LDC];
-    __shared__ T As[COOP ? 2 : 1][16][64];
+    constexpr int KC = 8;   // inner indices per staged chunk of the cooperative product
+    __shared__ T As[COOP ? 2 : 1][KC][64];
     Lx += blockIdx.y * lx_stride;
     info += 4 * blockIdx.y;
     pcount += (int64_t)blockIdx.y * nsplit;
     pbuf += (int64_t)blockIdx.y * npartial * 4096;
-    __shared__ T Bs[COOP ? 2 : 1][16][64];
+    __shared__ T Bs[COOP ? 2 : 1][KC][64];
     __shared__ int32_t s_rel[COOP ? 128 : 1];
     __shared__ int s_last;
 
@@ -783,7 +789,7 @@ __global__ __launch_bounds__(NT, COOP ? 2 : 3) void k_external(const Task *__res
                 if (tid == 0) atomicMin(info + 1, tk.J);
                 continue;
             }
-            coop_product(C, As, Bs, s_rel, in, imap, Lx, r0, nr, w);
+            coop_product<T, KC>(C, As, Bs, s_rel, in, imap, Lx, r0, nr, w);
         }
     }
 
