@@ -509,6 +509,7 @@ int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream)
     r->R.bpos = (int32_t *)(base + r->off_bpos);
     r->R.pend = (int32_t *)(base + r->off_pend);
     r->R.ntasks = (int64_t)r->tasks.size();
+    r->R.slots = sym::sweep_slots(r->h->P, r->tasks, true);
     hipError_t e = upload(r->R.tasks, r->tasks.data(), sizeof(sym::SolveTask) * r->tasks.size(), s);
     if (e == hipSuccess) e = upload(r->R.bpos, r->bpos.data(), sizeof(int32_t) * r->bpos.size(), s);
     if (e == hipSuccess) e = upload(r->R.pend, r->pend.data(), sizeof(int32_t) * r->pend.size(), s);

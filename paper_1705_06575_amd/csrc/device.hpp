@@ -66,6 +66,7 @@ struct DeviceRhs {
     int32_t *bpos = nullptr;        // nb_rhs: permuted positions of b's nonzeros
     int32_t *pend = nullptr;        // nb: initial counters of the pruned forward sweep
     int64_t ntasks = 0;
+    SweepSlots slots;               // ticket slots of the pruned forward sweep
 };
 
 // Optional per-launch event pairs for measurement: ev[2*i], ev[2*i+1]

@@ -115,6 +115,25 @@ struct Phase {
 constexpr int kTileRows = 64;   // T: rows per factor task tile
 constexpr int kSolveChunk = 256; // rows below the diagonal per forward-solve task
 
+// Ticket slots of a persistent sweep.  A workgroup takes one slot per
+// ticket: tasks [0, t1) go b1 to a slot, tasks [t1, t2) one to a slot and
+// tasks [t2, n) b2 to a slot (the last slot may hold fewer).  Runs of wide
+// levels (many independent tasks) are claimed in groups, so that the one
+// ticket counter does not serialize them; the chain of narrow levels keeps
+// one task per slot.  Slots are taken in task order and a task waits only
+// on tasks before it, so a slot's tasks run in order without deadlock.
+struct SweepSlots {
+    int64_t n = 0, t1 = 0, t2 = 0;
+    int32_t b1 = 1, b2 = 1;
+};
+constexpr int32_t kSlotGroup = 4;      // tasks per slot in a wide level
+constexpr int64_t kWideLevel = 2048;   // tasks that make a level wide
+
+inline int64_t slot_count(const SweepSlots &S)
+{
+    return S.t1 / S.b1 + (S.t2 - S.t1) + (S.n - S.t2 + S.b2 - 1) / S.b2;
+}
+
 struct SolveTask {      // 16 bytes: one chunk of one block in a sweep
     int32_t J;
     int32_t chunk;      // rows [w + chunk*kSolveChunk, ...) below the diagonal;
@@ -177,6 +196,7 @@ struct Plan {
     std::vector<int32_t> fwd_pend;      // nb: forward chunks whose rows meet the block
     std::vector<int32_t> bwd_pend;      // nb: off-diagonal chunks of the block
     std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers, then diagonals
+    SweepSlots fwd_slots, bwd_slots;    // ticket slots of the two dense sweeps
 
     // split external tiles: part descriptors, and the counts of arrival
     // counters and of 64 x 64 partial-tile slots they use
@@ -251,5 +271,10 @@ void nested_dissection(int32_t n, const std::vector<int64_t> &xadj,
 // Reach_L(beta) is the union of the elimination-tree paths from beta to the
 // roots.  Output: increasing order.
 void reach_etree(const Plan &P, const std::vector<int32_t> &beta, std::vector<int32_t> &out);
+
+// Slots of a sweep over `tasks` (contiguous runs of equal block level):
+// with bottom_first the leading run of wide levels is grouped, otherwise
+// the trailing one.
+SweepSlots sweep_slots(const Plan &P, const std::vector<SolveTask> &tasks, bool bottom_first);
 
 }  // namespace sym

@@ -284,15 +284,31 @@ __global__ void k_sync_reset(int32_t *__restrict__ pend, const int32_t *__restri
 // Next task of a persistent launch for the whole workgroup, or -1 when the
 // list is exhausted or some wait of this launch ran out (then every
 // workgroup stops taking tasks, so the launch ends promptly).
-__device__ __forceinline__ int next_ticket(int32_t *ticket, int *s_t, int ntasks, int32_t *err)
+__device__ __forceinline__ int next_ticket(int32_t *ticket, int *s_t, int nslots, int32_t *err)
 {
-    __syncthreads();                        // s_t of the previous task is no longer read
+    __syncthreads();                        // s_t of the previous slot is no longer read
     if (threadIdx.x == 0)
-        *s_t = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? ntasks
+        *s_t = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? nslots
                                                                                  : atomicAdd(ticket, 1);
     __syncthreads();
     const int t = *s_t;
-    return t < ntasks ? t : -1;
+    return t < nslots ? t : -1;
+}
+
+// Tasks [a, b) of ticket slot s.
+__device__ __forceinline__ void slot_tasks(const SweepSlots &S, int64_t s, int64_t &a, int64_t &b)
+{
+    const int64_t s1 = S.t1 / S.b1, s2 = s1 + (S.t2 - S.t1);
+    if (s < s1) {
+        a = s * S.b1;
+        b = a + S.b1;
+    } else if (s < s2) {
+        a = S.t1 + (s - s1);
+        b = a + 1;
+    } else {
+        a = S.t2 + (s - s2) * S.b2;
+        b = min(S.n, a + S.b2);
+    }
 }
 
 // Forward sweep, one persistent launch.  acc: right-hand side plus the
@@ -300,7 +316,7 @@ __device__ __forceinline__ int next_ticket(int32_t *ticket, int *s_t, int ntasks
 // counter is zero, atomically updated for the rows below); out: solved
 // values of the blocks' columns.
 template <typename T>
-__global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ tasks, SweepSlots S, int nslots,
                                                const int64_t *__restrict__ tptr,
                                                const int32_t *__restrict__ tgt,
                                                int32_t *__restrict__ pend, int32_t *ticket,
@@ -323,8 +339,12 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
     out += (int64_t)blockIdx.y * n;
     if (tid == 0) s_abort = 0;
     for (;;) {
-        const int t = next_ticket(ticket, &s_t, ntasks, err);
-        if (t < 0 || s_abort) break;
+        const int sl = next_ticket(ticket, &s_t, nslots, err);
+        if (sl < 0 || s_abort) break;
+        int64_t ta, tb;
+        slot_tasks(S, sl, ta, tb);
+        for (int64_t t = ta; t < tb; ++t) {
+        __syncthreads();                    // the previous task's LDS reads are done
         const SolveTask tk = tasks[t];
         const BlockDesc J = blk[tk.J];
         const int c0 = tk.c0;
@@ -367,6 +387,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         complete_then_sync();
         for (int64_t q = tptr[tk.list] + tid; q < tptr[tk.list + 1]; q += NT)
             __hip_atomic_fetch_add(&pend[tgt[q]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -374,7 +395,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
 // (levels from the top; per level the off-diagonal chunks, then the
 // diagonal solves).  x holds y on entry and the solution on exit.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tasks, SweepSlots S, int nslots,
                                                const int64_t *__restrict__ tptr,
                                                const int32_t *__restrict__ tgt,
                                                int32_t *__restrict__ pend, int32_t *done,
@@ -398,8 +419,12 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
     const int wave = tid >> 6;
     if (tid == 0) s_abort = 0;
     for (;;) {
-        const int t = next_ticket(ticket, &s_t, ntasks, err);
-        if (t < 0 || s_abort) break;
+        const int sl = next_ticket(ticket, &s_t, nslots, err);
+        if (sl < 0 || s_abort) break;
+        int64_t ta, tb;
+        slot_tasks(S, sl, ta, tb);
+        for (int64_t t = ta; t < tb; ++t) {
+        __syncthreads();                    // the previous task's LDS reads are done
         const SolveTask tk = tasks[t];
         const BlockDesc J = blk[tk.J];
         const T *L = Lx + J.valoff;
@@ -473,6 +498,7 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
             if (tid == 0)
                 __hip_atomic_store(&done[tk.J], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        }
     }
 }
 
@@ -492,14 +518,14 @@ inline unsigned sweep_grid(int64_t ntasks, int32_t m)
 }
 
 template <typename T>
-hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, int64_t ntasks,
+hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, const SweepSlots &S,
                     const int32_t *pend_init, double *acc, double *out, hipStream_t s)
 {
-    if (ntasks == 0) return hipGetLastError();
+    if (S.n == 0) return hipGetLastError();
     const unsigned m = (unsigned)D.m;
     k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, pend_init, nullptr, P.nb, D.ticket);
-    k_fwd_df<T><<<dim3(sweep_grid(ntasks, D.m), m), NT, 0, s>>>(
-        tasks, (int)ntasks, D.chunk_tptr, D.chunk_tgt, D.pend, D.ticket, D.info + 2, D.blk, D.rows,
+    k_fwd_df<T><<<dim3(sweep_grid(slot_count(S), D.m), m), NT, 0, s>>>(
+        tasks, S, (int)slot_count(S), D.chunk_tptr, D.chunk_tgt, D.pend, D.ticket, D.info + 2, D.blk, D.rows,
         (const T *)D.Lx, acc, out, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }
@@ -507,12 +533,12 @@ hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, 
 template <typename T>
 hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
 {
-    const int64_t ntasks = (int64_t)P.bwd_df.size();
-    if (ntasks == 0) return hipGetLastError();
+    const SweepSlots &S = P.bwd_slots;
+    if (S.n == 0) return hipGetLastError();
     const unsigned m = (unsigned)D.m;
     k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, D.bwd_pend, D.done, P.nb, D.ticket);
-    k_bwd_df<T><<<dim3(sweep_grid(ntasks, D.m), m), NT, 0, s>>>(
-        D.bwd_df, (int)ntasks, D.chunk_tptr, D.chunk_tgt, D.pend, D.done, D.ticket, D.info + 2,
+    k_bwd_df<T><<<dim3(sweep_grid(slot_count(S), D.m), m), NT, 0, s>>>(
+        D.bwd_df, S, (int)slot_count(S), D.chunk_tptr, D.chunk_tgt, D.pend, D.done, D.ticket, D.info + 2,
         D.blk, D.rows, (const T *)D.Lx, y, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }
@@ -535,9 +561,8 @@ hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double 
 
 hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *acc, double *out, hipStream_t s)
 {
-    const int64_t nt = (int64_t)P.fwd_tasks.size();
-    return P.precision == 1 ? fwd_impl<float>(P, D, D.fwd_tasks, nt, D.fwd_pend, acc, out, s)
-                            : fwd_impl<double>(P, D, D.fwd_tasks, nt, D.fwd_pend, acc, out, s);
+    return P.precision == 1 ? fwd_impl<float>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s)
+                            : fwd_impl<double>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s);
 }
 
 hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
@@ -551,8 +576,8 @@ hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs
 {
     if (P.n > 0) k_zero2<<<grid_for(P.n), 256, 0, s>>>(acc, out, P.n);
     if (nbeta > 0) k_place<<<grid_for(nbeta), 256, 0, s>>>(bv, R.bpos, acc, nbeta);
-    return P.precision == 1 ? fwd_impl<float>(P, D, R.tasks, R.ntasks, R.pend, acc, out, s)
-                            : fwd_impl<double>(P, D, R.tasks, R.ntasks, R.pend, acc, out, s);
+    return P.precision == 1 ? fwd_impl<float>(P, D, R.tasks, R.slots, R.pend, acc, out, s)
+                            : fwd_impl<double>(P, D, R.tasks, R.slots, R.pend, acc, out, s);
 }
 
 }  // namespace sym

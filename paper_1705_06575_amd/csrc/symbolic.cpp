@@ -720,6 +720,8 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q)
             P.bwd_df.push_back(SolveTask{P.level_blocks[q], -1, 0, -1});
     }
+    P.fwd_slots = sweep_slots(P, P.fwd_tasks, true);
+    P.bwd_slots = sweep_slots(P, P.bwd_df, false);
 
     // ------------------------------------------ descendant pairs (prune set)
     // Block K's rows below its own columns fall into runs of consecutive
@@ -866,6 +868,33 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
 
     P.analyze_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SYM_OK;
+}
+
+SweepSlots sweep_slots(const Plan &P, const std::vector<SolveTask> &tasks, bool bottom_first)
+{
+    SweepSlots S;
+    const int64_t n = (int64_t)tasks.size();
+    S.n = n;
+    S.t1 = 0;
+    S.t2 = n;
+    // runs of equal level: [run[i], run[i + 1])
+    std::vector<int64_t> run(1, 0);
+    for (int64_t i = 1; i < n; ++i)
+        if (P.blevel[tasks[i].J] != P.blevel[tasks[i - 1].J]) run.push_back(i);
+    if (n > 0) run.push_back(n);
+    const size_t nr = run.size() - 1;
+    if (bottom_first) {
+        size_t r = 0;
+        while (r < nr && run[r + 1] - run[r] >= kWideLevel) ++r;
+        S.b1 = kSlotGroup;
+        S.t1 = run[r] / kSlotGroup * kSlotGroup;
+    } else {
+        size_t r = nr;
+        while (r > 0 && run[r] - run[r - 1] >= kWideLevel) --r;
+        S.b2 = kSlotGroup;
+        S.t2 = run[r];
+    }
+    return S;
 }
 
 void reach_etree(const Plan &P, const std::vector<int32_t> &beta, std::vector<int32_t> &out)
