@@ -21,7 +21,7 @@ struct sym_plan {
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
            off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
-           off_parts = 0, off_pcount = 0, off_pbuf = 0,
+           off_parts = 0, off_pcount = 0, off_pbuf = 0, off_invb = 0,
            off_info = 0;
     sym::DevicePlan D;
     bool bound = false;
@@ -96,6 +96,7 @@ void layout(sym_plan *h)
     h->off_parts = take(sizeof(sym::PartDesc) * P.parts.size());
     h->off_pcount = take(sizeof(int32_t) * (size_t)P.nsplit);
     h->off_pbuf = take((size_t)P.npartial * 4096 * elem_size(P));
+    h->off_invb = take(sizeof(int32_t) * P.inv_blocks.size());
     h->ws_bytes = o;
 }
 
@@ -204,6 +205,7 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.parts = (sym::PartDesc *)(base + h->off_parts);
     D.pcount = (int32_t *)(base + h->off_pcount);
     D.pbuf = base + h->off_pbuf;
+    D.inv_blocks = (int32_t *)(base + h->off_invb);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
@@ -233,6 +235,8 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess && !P.ftasks.empty())
         e = hipMemsetAsync(D.ttime, 0, sizeof(uint64_t) * P.ftasks.size(), s);
     if (e == hipSuccess) e = upload(D.parts, P.parts.data(), sizeof(sym::PartDesc) * P.parts.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.inv_blocks, P.inv_blocks.data(), sizeof(int32_t) * P.inv_blocks.size(), s);
     if (e == hipSuccess && P.nsplit > 0)
         e = hipMemsetAsync(D.pcount, 0, sizeof(int32_t) * (size_t)P.nsplit, s);
     if (e == hipSuccess) e = upload(D.arowptr, P.arowptr.data(), sizeof(int64_t) * P.arowptr.size(), s);

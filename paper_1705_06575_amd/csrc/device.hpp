@@ -46,6 +46,7 @@ struct DevicePlan {
     double *vec6 = nullptr;         // n scratch: preconditioned residual z
     double *part = nullptr;         // kDotParts partial sums of a dot product
     uint64_t *ttime = nullptr;      // tasks: duration of each profiled external task (100 MHz ticks)
+    int32_t *inv_blocks = nullptr;  // nb: blocks for the diagonal inverses
     PartDesc *parts = nullptr;      // split external tiles' parts
     int32_t *pcount = nullptr;      // nsplit arrival counters (per instance)
     void *pbuf = nullptr;           // npartial 64 x 64 partial tiles, T (per instance)

@@ -971,6 +971,91 @@ __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
     tile_out(LJ + r0, X, J.ld, nr, w);
 }
 
+// The inverse of every diagonal block, for the triangular solves.  Its
+// strictly lower part is stored transposed in the block's upper triangle
+// (entry (i, j), i > j, at row j of column i), which the factorization
+// leaves unused; its diagonal (1 / L_ii) is not stored.
+// Blocks of at most 16 columns: one wavefront inverts the triangle.
+template <typename T>
+__global__ __launch_bounds__(64) void k_inverse_small(const int32_t *__restrict__ list,
+                                                      const BlockDesc *__restrict__ blk,
+                                                      T *__restrict__ Lx, int64_t lx_stride)
+{
+    __shared__ T D[16 * LDC];
+    __shared__ T M[272];
+    Lx += blockIdx.y * lx_stride;
+    const BlockDesc J = blk[list[blockIdx.x]];
+    const int w = J.w, lane = threadIdx.x;
+    const int64_t ld = J.ld;
+    T *L = Lx + J.valoff;
+    const int r = lane & 15, cq = lane >> 4;
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = cq + 4 * u;
+        const bool ok = r < w && c < w && r >= c;
+        const T x = L[ok ? (int64_t)c * ld + r : 0];
+        v[u] = ok ? x : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) D[(cq + 4 * u) * LDC + r] = v[u];
+    __syncthreads();
+    wave_tri_inverse(D, 0, w, M);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = cq + 4 * u;
+        if (r < i && i < w) L[(int64_t)i * ld + r] = M[i * 17 + r];
+    }
+}
+
+// Wider blocks: X := I L_JJ^{-T} = (L_JJ^{-1})^T with the off-diagonal
+// solve's routines (16 x 16 diagonal triangles inverted by the four
+// wavefronts, then each solves 16 rows on the matrix cores); X's strictly
+// upper part is the stored layout.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_inverse_big(const int32_t *__restrict__ list,
+                                                    const BlockDesc *__restrict__ blk,
+                                                    T *__restrict__ Lx, int64_t lx_stride)
+{
+    __shared__ T D[64 * LDC];
+    __shared__ T X[64 * LDC];
+    __shared__ T M[4 * 272];
+    Lx += blockIdx.y * lx_stride;
+    const BlockDesc J = blk[list[blockIdx.x]];
+    const int w = J.w;
+    const int64_t ld = J.ld;
+    T *L = Lx + J.valoff;
+    const int tid = threadIdx.x;
+    {
+        const int i = tid & 63, c0 = tid >> 6;
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = c0 + 4 * u;
+            const bool ok = i < w && c < w && i >= c;
+            const T x = L[ok ? (int64_t)c * ld + i : 0];
+            v[u] = ok ? x : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = c0 + 4 * u;
+            D[c * LDC + i] = v[u];
+            X[c * LDC + i] = (i == c && i < w) ? T(1) : T(0);
+        }
+    }
+    __syncthreads();
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (16 * wv < w) wave_tri_inverse(D, 16 * wv, min(16, w - 16 * wv), M + 272 * wv);
+    __syncthreads();
+    if (16 * wv < w) wave_rows_solve(X, D, M, 16 * wv, w);
+    __syncthreads();
+    for (int k = tid; k < 4096; k += NT) {
+        const int i = k & 63, c = k >> 6;
+        if (i < c && c < w) L[(int64_t)c * ld + i] = X[c * LDC + i];
+    }
+}
+
 inline unsigned grid_for(int64_t count, int per = 256)
 {
     int64_t g = (count + per - 1) / per;
@@ -1035,6 +1120,14 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
             k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs);
         else
             k_trsm<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, lxs);
+    }
+    if (P.nb > 0) {
+        Bracket b(prof, s, 2);
+        const int32_t nsm = P.inv_nsmall, nbig = P.nb - P.inv_nsmall;
+        if (nsm > 0)
+            k_inverse_small<T><<<dim3((unsigned)nsm, m), 64, 0, s>>>(D.inv_blocks, D.blk, Lx, lxs);
+        if (nbig > 0)
+            k_inverse_big<T><<<dim3((unsigned)nbig, m), NT, 0, s>>>(D.inv_blocks + nsm, D.blk, Lx, lxs);
     }
     return hipGetLastError();
 }

@@ -200,6 +200,8 @@ struct Plan {
 
     // split external tiles: part descriptors, and the counts of arrival
     // counters and of 64 x 64 partial-tile slots they use
+    std::vector<int32_t> inv_blocks;    // blocks of <= 16 columns, then the wider ones
+    int32_t inv_nsmall = 0;             // blocks of <= 16 columns in inv_blocks
     std::vector<PartDesc> parts;
     int32_t nsplit = 0;
     int64_t npartial = 0;

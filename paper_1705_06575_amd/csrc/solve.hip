@@ -12,21 +12,25 @@
 //
 // Each sweep is one persistent launch driven by data flow, not one launch
 // per level.  Workgroups take tasks by ticket (an atomic counter) in a
-// topological order; a task waits, with a bounded spin, until what it reads
-// is final, and signals what it produced:
+// topological order (the tasks of wide levels several to a ticket); a task
+// waits, with a bounded spin, until what it reads is final, and signals
+// what it produced.  The diagonal triangles are solved with the inverse of
+// each diagonal block, which the factorization stores in the block's unused
+// upper triangle: one small matrix-vector product per block instead of a
+// chain of w dependent steps.
 //   forward, task (block J, chunk of 256 rows below its diagonal): waits
 //   until every chunk whose rows meet J's columns has added its update into
 //   the accumulator (a per-block counter reaching zero); stages J's
-//   diagonal triangle in LDS and fetches its rows' L values before waiting;
-//   wavefront 0 solves the triangle (lane k owns y_k; every chunk of J
-//   repeats this small solve); chunk 0 stores y_J; every thread subtracts
+//   diagonal block in LDS and fetches its rows' L values before waiting;
+//   wavefront 0 forms y_J = L_JJ^{-1} (accumulator) (every chunk of J
+//   repeats this small product); chunk 0 stores y_J; every thread subtracts
 //   sum_k L_ik y_k from its row's accumulator entry (one atomic add); then
 //   it decrements the counter of every block its rows fall in.
 //   backward (L^T x = y), levels from the top: chunk tasks of J wait for the
 //   blocks owning their rows to be final, subtract their share of
 //   L_offdiag^T x from J's entries (atomics) and decrement J's counter;
-//   J's diagonal task waits for that counter, solves the transposed
-//   triangle and marks J final.
+//   J's diagonal task waits for that counter, applies L_JJ^{-T} and marks
+//   J final.
 // A task only waits for tasks with smaller tickets, which running
 // workgroups hold, so the launch always drains; a wait that exceeds its
 // bound (a corrupt plan) records an error and ends the launch.  Counters
@@ -49,19 +53,13 @@ namespace {
 constexpr int NT = 256;
 constexpr int LDT = 65;                 // LDS stride of a staged diagonal triangle
 
-__device__ __forceinline__ double lane_value(double v, int src)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Stage the lower triangle of a w x w diagonal block (global, leading
-// dimension ld, columns from c0 on) into LDS as doubles.  All loads are
+// Stage the upper triangle (diagonal included) of a w x w diagonal block,
+// rows from c0 on, into LDS as doubles (column-major, stride LDT).  The
+// factorization leaves there the inverse of the block's lower triangle,
+// transposed: entry (j, i), j < i, holds (L_JJ^{-1})_ij.  All loads are
 // issued before the first store (one memory latency per block).
 template <typename T>
-__device__ __forceinline__ void stage_tri(double *D, const T *__restrict__ L, int64_t ld, int w,
+__device__ __forceinline__ void stage_inv(double *D, const T *__restrict__ L, int64_t ld, int w,
                                           int c0)
 {
     const int i = threadIdx.x & 63, cq = threadIdx.x >> 6;
@@ -69,7 +67,7 @@ __device__ __forceinline__ void stage_tri(double *D, const T *__restrict__ L, in
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int c = cq + 4 * u;
-        const bool ok = i < w && c < w && i >= c && c >= c0;
+        const bool ok = i < w && c < w && i <= c && i >= c0;
         const T val = L[ok ? (int64_t)c * ld + i : 0];
         v[u] = ok ? (double)val : 0.0;
     }
@@ -80,107 +78,46 @@ __device__ __forceinline__ void stage_tri(double *D, const T *__restrict__ L, in
     }
 }
 
-// sum_{k = c0}^{w-1} L[k * ld + i] * ys[k] with the loads of 16 columns
-// issued together.
-template <typename T>
-__device__ __forceinline__ double row_dot(const T *__restrict__ L, int64_t ld, int64_t i,
-                                          const double *ys, int c0, int w)
-{
-    double s = 0.0;
-    for (int k0 = c0; k0 < w; k0 += 16) {
-        double lv[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k = k0 + j;
-            const T val = L[(k < w ? (int64_t)k * ld : 0) + i];
-            lv[j] = k < w ? (double)val : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (k0 + j < w) s += lv[j] * ys[k0 + j];
-    }
-    return s;
-}
-
-// The same for exactly the 32 columns [c0, c0 + 32) (those past w read as
-// 0), all loads issued together.
-template <typename T>
-__device__ __forceinline__ double row_dot32(const T *__restrict__ L, int64_t ld, int64_t i,
-                                            const double *ys, int c0, int w)
-{
-    double lv[32];
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-        const int k = min(c0 + j, w - 1);
-        lv[j] = (double)L[(int64_t)k * ld + i];
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < 32; ++j)
-        if (c0 + j < w) s += lv[j] * ys[c0 + j];
-    return s;
-}
-
-// Forward substitution with the staged triangle D (stride LDT) by one
-// wavefront: lane i holds entry i of the right-hand side in v and
-// 1 / D[i][i] in rd, and returns y_i.  The columns are walked in groups of
-// 16 whose entries for this lane are read from LDS one group ahead, so each
-// step of the dependence chain is a cross-lane read, a product and a fused
-// multiply-add.
-__device__ __forceinline__ double tri_forward(const double *D, double v, double rd, int c0, int w)
+// y = L_JJ^{-1} v for the block staged by stage_inv, by one wavefront:
+// lane i holds v_i in v and 1 / L_ii in rd and returns
+// y_i = v_i / L_ii + sum_{j < i} (L_JJ^{-1})_ij v_j (v_j = 0 below c0).  The
+// entries of v are read as LDS broadcasts from vb; four partial sums.
+__device__ __forceinline__ double tri_forward(const double *D, double *vb, double v, double rd,
+                                              int c0, int w)
 {
     const int lane = threadIdx.x & 63;
-    double dn[16];
-    const int g0 = c0 & ~15;
+    vb[lane] = v;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    double s[4] = {rd * v, 0.0, 0.0, 0.0};
+    for (int j0 = c0 & ~3; j0 < w; j0 += 4) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) dn[j] = D[(g0 + j) * LDT + lane];
-    for (int g = g0; g < w; g += 16) {
-        double dc[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) dc[j] = dn[j];
-        if (g + 16 < w) {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) dn[j] = D[(g + 16 + j) * LDT + lane];
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k = g + j;
-            if (k >= c0 && k < w) {
-                const double xk = lane_value(v, k) * lane_value(rd, k);
-                v = lane == k ? xk : (lane > k ? v - dc[j] * xk : v);
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int j = min(j0 + u, 63);
+            const double c = j0 + u < lane ? D[lane * LDT + j] : 0.0;
+            s[u] = fma(c, vb[j], s[u]);
         }
     }
-    return v;
+    return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// Backward substitution with the transposed triangle: lane i's entries of
-// row i of D are read one group of 16 columns ahead.
-__device__ __forceinline__ double tri_backward(const double *D, double v, double rd, int w)
+// x = L_JJ^{-T} v for the block staged by stage_inv (c0 = 0), by one
+// wavefront: lane j returns x_j = v_j / L_jj + sum_{i > j} (L_JJ^{-1})_ij v_i.
+__device__ __forceinline__ double tri_backward(const double *D, double *vb, double v, double rd,
+                                               int w)
 {
     const int lane = threadIdx.x & 63;
-    double dn[16];
-    const int gl = (w - 1) & ~15;
+    vb[lane] = v;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    double s[4] = {rd * v, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < w; i0 += 4) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) dn[j] = D[lane * LDT + gl + j];
-    for (int g = gl; g >= 0; g -= 16) {
-        double dc[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) dc[j] = dn[j];
-        if (g >= 16) {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) dn[j] = D[lane * LDT + g - 16 + j];
-        }
-#pragma unroll
-        for (int j = 15; j >= 0; --j) {
-            const int k = g + j;
-            if (k < w) {
-                const double xk = lane_value(v, k) * lane_value(rd, k);
-                v = lane == k ? xk : (lane < k ? v - dc[j] * xk : v);
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int i = min(i0 + u, 63);
+            const double c = i0 + u > lane && i0 + u < w ? D[i * LDT + lane] : 0.0;
+            s[u] = fma(c, vb[i], s[u]);
         }
     }
-    return v;
+    return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict__ perm,
@@ -327,7 +264,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
                                                int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
-    __shared__ double ys[64];
+    __shared__ double ys[64], vb[64];
     __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
     // instance blockIdx.y of a batch
@@ -353,36 +290,35 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         const int w = J.w;
         // what does not depend on other tasks: the triangle, this thread's
         // row index and the row's first 32 values
-        stage_tri(D, L, ld, w, c0);
+        stage_inv(D, L, ld, w, c0);
         const int i = w + tk.chunk * NT + tid;
         const bool has_row = i < J.r;
         const int ic = has_row ? i : w - 1;
         const int32_t row = rows[J.rowoff + ic];
-        double lv[32];
+        double lv[64];
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
+        for (int j = 0; j < 64; ++j) {
             const int k = min(c0 + j, w - 1);
             lv[j] = (double)L[(int64_t)k * ld + ic];
         }
         __syncthreads();                    // the staged triangle is readable
-        const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
+        const double rd = (tid >= c0 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
         if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
         __syncthreads();
         if (s_abort) break;
         if (tid < 64) {
             double v = (tid >= c0 && tid < w) ? coherent_load(&acc[J.col0 + tid]) : 0.0;
-            v = tri_forward(D, v, rd, c0, w);
+            v = tri_forward(D, vb, v, rd, c0, w);
             ys[tid] = v;
             if (tk.chunk == 0 && tid >= c0 && tid < w) out[J.col0 + tid] = v;
         }
         __syncthreads();
         if (has_row) {
-            double s = 0.0;
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < 32; ++j)
-                if (c0 + j < w) s += lv[j] * ys[c0 + j];
-            if (c0 + 32 < w) s += row_dot32(L, ld, i, ys, c0 + 32, w);
-            atomicAdd(&acc[row], -s);
+            for (int j = 0; j < 64; ++j)
+                if (c0 + j < w) s4[j & 3] = fma(lv[j], ys[c0 + j], s4[j & 3]);
+            atomicAdd(&acc[row], -((s4[0] + s4[1]) + (s4[2] + s4[3])));
         }
         complete_then_sync();
         for (int64_t q = tptr[tk.list] + tid; q < tptr[tk.list + 1]; q += NT)
@@ -406,6 +342,7 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
                                                int32_t nb, int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
+    __shared__ double vb[64];
     __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
     // instance blockIdx.y of a batch
@@ -483,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
             if (tid == 0)
                 __hip_atomic_fetch_add(&pend[tk.J], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            stage_tri(D, L, ld, w, 0);
+            stage_inv(D, L, ld, w, 0);
             __syncthreads();
             const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
             if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
@@ -491,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
             if (s_abort) break;
             if (tid < 64) {
                 double v = tid < w ? coherent_load(&x[J.col0 + tid]) : 0.0;
-                v = tri_backward(D, v, rd, w);
+                v = tri_backward(D, vb, v, rd, w);
                 if (tid < w) coherent_store(&x[J.col0 + tid], v);
             }
             complete_then_sync();

@@ -69,6 +69,13 @@ void permute_lower(int32_t n, const int64_t *Ap, const int32_t *Ai,
 void build_schedule(Plan &P)
 {
     const int32_t B = P.B;
+    // blocks whose inverse one wavefront forms, then the wider ones
+    P.inv_blocks.clear();
+    for (int32_t b = 0; b < P.nb; ++b)
+        if (P.blk[b].w <= 16) P.inv_blocks.push_back(b);
+    P.inv_nsmall = (int32_t)P.inv_blocks.size();
+    for (int32_t b = 0; b < P.nb; ++b)
+        if (P.blk[b].w > 16) P.inv_blocks.push_back(b);
     P.parts.clear();
     P.nsplit = 0;
     P.npartial = 0;
