@@ -195,7 +195,7 @@ struct Plan {
     std::vector<int32_t> chunk_tgt;
     std::vector<int32_t> fwd_pend;      // nb: forward chunks whose rows meet the block
     std::vector<int32_t> bwd_pend;      // nb: off-diagonal chunks of the block
-    std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers, then diagonals
+    std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers (the last of a block finishes it), then blocks without rows below
     SweepSlots fwd_slots, bwd_slots;    // ticket slots of the two dense sweeps
 
     // split external tiles: part descriptors, and the counts of arrival

@@ -28,9 +28,9 @@
 //   it decrements the counter of every block its rows fall in.
 //   backward (L^T x = y), levels from the top: chunk tasks of J wait for the
 //   blocks owning their rows to be final, subtract their share of
-//   L_offdiag^T x from J's entries (atomics) and decrement J's counter;
-//   J's diagonal task waits for that counter, applies L_JJ^{-T} and marks
-//   J final.
+//   L_offdiag^T x from J's entries (atomics) and decrement J's counter; the
+//   chunk that empties the counter applies L_JJ^{-T} and marks J final (a
+//   block without rows below its columns has a task of its own for that).
 // A task only waits for tasks with smaller tickets, which running
 // workgroups hold, so the launch always drains; a wait that exceeds its
 // bound (a corrupt plan) records an error and ends the launch.  Counters
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
 // (levels from the top; per level the off-diagonal chunks, then the
 // diagonal solves).  x holds y on entry and the solution on exit.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tasks, SweepSlots S, int nslots,
+__global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ tasks, SweepSlots S, int nslots,
                                                const int64_t *__restrict__ tptr,
                                                const int32_t *__restrict__ tgt,
                                                int32_t *__restrict__ pend, int32_t *done,
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
 {
     __shared__ double D[64 * LDT];
     __shared__ double vb[64];
-    __shared__ int s_t, s_abort;
+    __shared__ int s_t, s_abort, s_last;
     const int tid = threadIdx.x;
     // instance blockIdx.y of a batch
     pend += (int64_t)blockIdx.y * nb;
@@ -367,17 +367,29 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
         const T *L = Lx + J.valoff;
         const int64_t ld = J.ld;
         const int w = J.w;
+        // the diagonal block's inverse, for the task that finishes J
+        stage_inv(D, L, ld, w, 0);
+        bool finish = true;
         if (tk.chunk >= 0) {
             // subtract sum_{i in chunk} L_ik x[row_i] from x[J's column k]:
-            // wavefront v takes columns v, v + 4, ..., lanes take rows
+            // wavefront v takes columns v, v + 4, ..., lanes take rows; the
+            // factor values are fetched before the wait
             const int i0 = w + tk.chunk * NT;
             const int i1 = min(J.r, i0 + NT);
             const int32_t *rJ = rows + J.rowoff;
             int32_t ri[4];
+            double lvv[4][16];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + lane + 64 * u;
-                ri[u] = rJ[i < i1 ? i : i0];
+                const int ic = i < i1 ? i : i0;
+                ri[u] = rJ[ic];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int k = wave + 4 * q;
+                    const T val = L[(k < w ? (int64_t)k * ld : 0) + ic];
+                    lvv[u][q] = k < w ? (double)val : 0.0;
+                }
             }
             // the blocks owning the chunk's rows must be final
             bool ok = true;
@@ -395,18 +407,8 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
             }
             double part[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) part[q] = 0.0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + lane + 64 * u;
-                const int ic = i < i1 ? i : i0;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int k = wave + 4 * q;
-                    const T val = L[(k < w ? (int64_t)k * ld : 0) + ic];
-                    part[q] += (k < w ? (double)val : 0.0) * xr[u];
-                }
-            }
+            for (int q = 0; q < 16; ++q)
+                part[q] = fma(lvv[0][q], xr[0], lvv[1][q] * xr[1]) + fma(lvv[2][q], xr[2], lvv[3][q] * xr[3]);
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int k = wave + 4 * q;
@@ -416,16 +418,23 @@ __global__ __launch_bounds__(NT) void k_bwd_df(const SolveTask *__restrict__ tas
                     if (lane == 0) atomicAdd(&x[J.col0 + k], -s2);
                 }
             }
+            // the chunk whose decrement empties J's counter finishes J (the
+            // others' updates completed before their decrements)
             complete_then_sync();
             if (tid == 0)
-                __hip_atomic_fetch_add(&pend[tk.J], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            stage_inv(D, L, ld, w, 0);
+                s_last = __hip_atomic_fetch_add(&pend[tk.J], -1, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) == 1;
             __syncthreads();
-            const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
+            finish = s_last != 0;
+        } else {
+            // a block without rows below its columns
+            __syncthreads();
             if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
             __syncthreads();
             if (s_abort) break;
+        }
+        if (finish) {
+            const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
             if (tid < 64) {
                 double v = tid < w ? coherent_load(&x[J.col0 + tid]) : 0.0;
                 v = tri_backward(D, vb, v, rd, w);

@@ -724,8 +724,11 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
             P.bwd_pend[b] = nch;
             for (int32_t c = 0; c < nch; ++c) P.bwd_df.push_back(SolveTask{b, c, 0, P.fwd_first[b] + c});
         }
+        // the last of a block's chunks finishes it; blocks without chunks
+        // get a task of their own
         for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q)
-            P.bwd_df.push_back(SolveTask{P.level_blocks[q], -1, 0, -1});
+            if (P.bwd_pend[P.level_blocks[q]] == 0)
+                P.bwd_df.push_back(SolveTask{P.level_blocks[q], -1, 0, -1});
     }
     P.fwd_slots = sweep_slots(P, P.fwd_tasks, true);
     P.bwd_slots = sweep_slots(P, P.bwd_df, false);
