@@ -78,46 +78,31 @@ __device__ __forceinline__ void stage_inv(double *D, const T *__restrict__ L, in
     }
 }
 
-// y = L_JJ^{-1} v for the block staged by stage_inv, by one wavefront:
-// lane i holds v_i in v and 1 / L_ii in rd and returns
-// y_i = v_i / L_ii + sum_{j < i} (L_JJ^{-1})_ij v_j (v_j = 0 below c0).  The
-// entries of v are read as LDS broadcasts from vb; four partial sums.
-__device__ __forceinline__ double tri_forward(const double *D, double *vb, double v, double rd,
-                                              int c0, int w)
+// The diagonal block's inverse applied to v (staged by stage_inv; v in
+// vb, zero outside [c0, w)), by the whole workgroup: wavefront q forms, for
+// every row i (its lane), the partial sum over the 16 columns
+// [16q, 16q + 16) and leaves it in pp[q][i]; the caller adds the four
+// partials and v_i / L_ii.  Forward: y = L_JJ^{-1} v, row i takes
+// (L_JJ^{-1})_ij v_j for j < i (stored at D[i * LDT + j]).  Backward:
+// x = L_JJ^{-T} v, row j takes (L_JJ^{-1})_ij v_i for i > j (stored at
+// D[i * LDT + j]).
+__device__ __forceinline__ void inv_partials(const double *D, const double *vb, double *pp, int c0,
+                                             int w, bool transposed)
 {
     const int lane = threadIdx.x & 63;
-    vb[lane] = v;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    double s[4] = {rd * v, 0.0, 0.0, 0.0};
-    for (int j0 = c0 & ~3; j0 < w; j0 += 4) {
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j0 = max(16 * q, c0 & ~3), j1 = min(16 * q + 16, w);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int jb = j0; jb < j1; jb += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int j = min(j0 + u, 63);
-            const double c = j0 + u < lane ? D[lane * LDT + j] : 0.0;
+            const int j = min(jb + u, 63);
+            const bool in = jb + u < j1 && (transposed ? jb + u > lane : jb + u < lane);
+            const double c = in ? (transposed ? D[j * LDT + lane] : D[lane * LDT + j]) : 0.0;
             s[u] = fma(c, vb[j], s[u]);
         }
     }
-    return (s[0] + s[1]) + (s[2] + s[3]);
-}
-
-// x = L_JJ^{-T} v for the block staged by stage_inv (c0 = 0), by one
-// wavefront: lane j returns x_j = v_j / L_jj + sum_{i > j} (L_JJ^{-1})_ij v_i.
-__device__ __forceinline__ double tri_backward(const double *D, double *vb, double v, double rd,
-                                               int w)
-{
-    const int lane = threadIdx.x & 63;
-    vb[lane] = v;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    double s[4] = {rd * v, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < w; i0 += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = min(i0 + u, 63);
-            const double c = i0 + u > lane && i0 + u < w ? D[i * LDT + lane] : 0.0;
-            s[u] = fma(c, vb[i], s[u]);
-        }
-    }
-    return (s[0] + s[1]) + (s[2] + s[3]);
+    pp[q * 64 + lane] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict__ perm,
@@ -264,7 +249,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
                                                int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
-    __shared__ double ys[64], vb[64];
+    __shared__ double ys[64], vb[64], pp[256];
     __shared__ int s_t, s_abort;
     const int tid = threadIdx.x;
     // instance blockIdx.y of a batch
@@ -306,10 +291,13 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
         __syncthreads();
         if (s_abort) break;
+        if (tid < 64) vb[tid] = (tid >= c0 && tid < w) ? coherent_load(&acc[J.col0 + tid]) : 0.0;
+        __syncthreads();
+        inv_partials(D, vb, pp, c0, w, false);
+        __syncthreads();
         if (tid < 64) {
-            double v = (tid >= c0 && tid < w) ? coherent_load(&acc[J.col0 + tid]) : 0.0;
-            v = tri_forward(D, vb, v, rd, c0, w);
-            ys[tid] = v;
+            const double v = rd * vb[tid] + ((pp[tid] + pp[64 + tid]) + (pp[128 + tid] + pp[192 + tid]));
+            ys[tid] = tid >= c0 && tid < w ? v : 0.0;
             if (tk.chunk == 0 && tid >= c0 && tid < w) out[J.col0 + tid] = v;
         }
         __syncthreads();
@@ -342,7 +330,7 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
                                                int32_t nb, int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
-    __shared__ double vb[64];
+    __shared__ double vb[64], pp[256];
     __shared__ int s_t, s_abort, s_last;
     const int tid = threadIdx.x;
     // instance blockIdx.y of a batch
@@ -435,10 +423,13 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
         }
         if (finish) {
             const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
-            if (tid < 64) {
-                double v = tid < w ? coherent_load(&x[J.col0 + tid]) : 0.0;
-                v = tri_backward(D, vb, v, rd, w);
-                if (tid < w) coherent_store(&x[J.col0 + tid], v);
+            if (tid < 64) vb[tid] = tid < w ? coherent_load(&x[J.col0 + tid]) : 0.0;
+            __syncthreads();
+            inv_partials(D, vb, pp, 0, w, true);
+            __syncthreads();
+            if (tid < w) {
+                const double v = rd * vb[tid] + ((pp[tid] + pp[64 + tid]) + (pp[128 + tid] + pp[192 + tid]));
+                coherent_store(&x[J.col0 + tid], v);
             }
             complete_then_sync();
             if (tid == 0)
