@@ -273,8 +273,8 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         const T *L = Lx + J.valoff;
         const int64_t ld = J.ld;
         const int w = J.w;
-        // what does not depend on other tasks: the triangle, this thread's
-        // row index and the row's first 32 values
+        // what does not depend on other tasks: the diagonal block, this thread's
+        // row index and the row's 64 values (columns past w repeat the last)
         stage_inv(D, L, ld, w, c0);
         const int i = w + tk.chunk * NT + tid;
         const bool has_row = i < J.r;
@@ -282,10 +282,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         const int32_t row = rows[J.rowoff + ic];
         double lv[64];
 #pragma unroll
-        for (int j = 0; j < 64; ++j) {
-            const int k = min(c0 + j, w - 1);
-            lv[j] = (double)L[(int64_t)k * ld + ic];
-        }
+        for (int k = 0; k < 64; ++k) lv[k] = (double)L[(int64_t)min(k, w - 1) * ld + ic];
         __syncthreads();                    // the staged triangle is readable
         const double rd = (tid >= c0 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
         if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
@@ -302,10 +299,10 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         }
         __syncthreads();
         if (has_row) {
+            // y is 0 outside [c0, w): all 64 columns take part, branch-free
             double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < 64; ++j)
-                if (c0 + j < w) s4[j & 3] = fma(lv[j], ys[c0 + j], s4[j & 3]);
+            for (int k = 0; k < 64; ++k) s4[k & 3] = fma(lv[k], ys[k], s4[k & 3]);
             atomicAdd(&acc[row], -((s4[0] + s4[1]) + (s4[2] + s4[3])));
         }
         complete_then_sync();
