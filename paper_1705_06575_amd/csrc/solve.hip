@@ -394,16 +394,29 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
 #pragma unroll
             for (int q = 0; q < 16; ++q)
                 part[q] = fma(lvv[0][q], xr[0], lvv[1][q] * xr[1]) + fma(lvv[2][q], xr[2], lvv[3][q] * xr[3]);
-            // sums over the 64 lanes, unconditionally (no branch between
-            // the exchanges), then one atomic per column of J
+            // sums over the 64 lanes, then one atomic per column of J: for
+            // wide blocks all 16 columns without branches between the
+            // exchanges, for narrow ones only the columns the block has
+            if (w > 32) {
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1)
+                for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) part[q] += __shfl_xor(part[q], off);
-            if (lane == 0) {
+                    for (int q = 0; q < 16; ++q) part[q] += __shfl_xor(part[q], off);
+                if (lane == 0) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    if (wave + 4 * q < w) atomicAdd(&x[J.col0 + wave + 4 * q], -part[q]);
+                    for (int q = 0; q < 16; ++q)
+                        if (wave + 4 * q < w) atomicAdd(&x[J.col0 + wave + 4 * q], -part[q]);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int k = wave + 4 * q;
+                    if (k < w) {
+                        double s2 = part[q];
+                        for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+                        if (lane == 0) atomicAdd(&x[J.col0 + k], -s2);
+                    }
+                }
             }
             // the chunk whose decrement empties J's counter finishes J (the
             // others' updates completed before their decrements)
