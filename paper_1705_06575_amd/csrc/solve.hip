@@ -274,15 +274,23 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         const int64_t ld = J.ld;
         const int w = J.w;
         // what does not depend on other tasks: the diagonal block, this thread's
-        // row index and the row's 64 values (columns past w repeat the last)
+        // row index and the row's values (columns past w repeat the last)
         stage_inv(D, L, ld, w, c0);
         const int i = w + tk.chunk * NT + tid;
         const bool has_row = i < J.r;
         const int ic = has_row ? i : w - 1;
         const int32_t row = rows[J.rowoff + ic];
+        const bool wide = w > 16;
         double lv[64];
 #pragma unroll
-        for (int k = 0; k < 64; ++k) lv[k] = (double)L[(int64_t)min(k, w - 1) * ld + ic];
+        for (int k = 0; k < 16; ++k) lv[k] = (double)L[(int64_t)min(k, w - 1) * ld + ic];
+        if (wide) {
+#pragma unroll
+            for (int k = 16; k < 64; ++k) lv[k] = (double)L[(int64_t)min(k, w - 1) * ld + ic];
+        } else {
+#pragma unroll
+            for (int k = 16; k < 64; ++k) lv[k] = 0.0;
+        }
         __syncthreads();                    // the staged triangle is readable
         const double rd = (tid >= c0 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
         if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
@@ -299,10 +307,15 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
         }
         __syncthreads();
         if (has_row) {
-            // y is 0 outside [c0, w): all 64 columns take part, branch-free
+            // y is 0 outside [c0, w): all 64 (narrow blocks: 16) columns
+            // take part, branch-free
             double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int k = 0; k < 64; ++k) s4[k & 3] = fma(lv[k], ys[k], s4[k & 3]);
+            for (int k = 0; k < 16; ++k) s4[k & 3] = fma(lv[k], ys[k], s4[k & 3]);
+            if (wide) {
+#pragma unroll
+                for (int k = 16; k < 64; ++k) s4[k & 3] = fma(lv[k], ys[k], s4[k & 3]);
+            }
             atomicAdd(&acc[row], -((s4[0] + s4[1]) + (s4[2] + s4[3])));
         }
         complete_then_sync();
