@@ -101,6 +101,8 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream);
  * left-looking Cholesky with dense factorization of each diagonal block and
  * dense triangular solves for the rows below it).  Ax_dev: device
  * double[nnz(A)] in the order of the Ai given to sym_analyze.  Asynchronous.
+ * The factorization ends by storing, for the triangular solves, the inverse
+ * of each diagonal block in the block's otherwise unused upper triangle.
  * A non-positive pivot is not an error return: it is recorded on the device
  * and reported by sym_status.  Errors: SYM_EINVAL, SYM_ESTATE (not bound),
  * SYM_EHIP.
