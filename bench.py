@@ -13,8 +13,10 @@ sparse right-hand side of 1% random nonzeros.
 Prints ONE JSON line.  `value` is the step's FP64 arithmetic (sum_j |L_j|^2
 for the factor plus 2 flops per stored entry of L per sweep) per second.
 Extra fields give each part separately; `roofline` covers the dominant
-kernel of the factor, timed with HIP events on the library's stream during
-the timed steps; `cpu_baseline` is the CPU oracle timed on a bounded sample.
+kernel of the factor, timed with HIP events on the library's stream around
+every launch of the last timed step's factorization (read after the timed
+loop, so that no step waits for the host); `cpu_baseline` is the CPU oracle
+timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -380,19 +382,19 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    an.profile(True)
+    an.profile(True)                           # creates the events
+    an.profile(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prof_ms = {k: 0.0 for k in S.Analysis.PROFILE_KINDS}
-    prof_n = {k: 0 for k in S.Analysis.PROFILE_KINDS}
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        if i == args.steps - 1:
+            an.profile(True)                   # events around the last step's launches
         step()
-        ms, n, kflops = an.profile_read()      # waits on this factor's last event only
-        for k in ms:
-            prof_ms[k] += ms[k]
-            prof_n[k] += n[k]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # per-launch event times of the last timed step's factorization (read
+    # after the loop, so that no step waits for the host)
+    prof_ms, prof_n, kflops = an.profile_read()
     an.profile(False)
     assert an.status() == 0
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -424,10 +426,10 @@ def main():
     touched = np.unique(col2blk[reach])
     bytes_sparse = 8.0 * nnzL_reach + 4.0 * float(rows_per_block[touched].sum()) + 16.0 * reach.size
 
-    # dominant kernel of the factor, from the live events of the timed steps
+    # dominant kernel of the factor, from the live events of the last timed step
     dom = max((k for k in prof_ms if k != "scatter"), key=lambda k: prof_ms[k])
     dom_ms_per_launch = prof_ms[dom] / max(prof_n[dom], 1)
-    dom_flops_per_launch = kflops[dom] * args.steps / max(prof_n[dom], 1)
+    dom_flops_per_launch = kflops[dom] / max(prof_n[dom], 1)
     achieved = dom_flops_per_launch / (dom_ms_per_launch * 1e-3) / 1e12
 
     out = {
@@ -458,8 +460,8 @@ def main():
         "sptrsv_fwd_sparse_gbps": round(bytes_sparse / (t_sparse * 1e-3) / 1e9, 2),
         "full_solve_ms": round(t_solve, 4),
         "analyze_s": round(analyze_s, 3),
-        "factor_kernels_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof_ms.items()},
-        "factor_launches_per_step": {k: v // args.steps for k, v in prof_n.items()},
+        "factor_kernels_ms_per_step": {k: round(v, 3) for k, v in prof_ms.items()},
+        "factor_launches_per_step": dict(prof_n),
         "roofline": {"kernel": f"factor {dom} update (k_{dom})", "bound": "mfma",
                      "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5),

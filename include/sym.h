@@ -242,7 +242,8 @@ int sym_stat(sym_handle h, int what, double *value);
  * the stream and returns, for the most recent sym_factor, the summed event
  * time in ms and the launch count of each kernel kind:
  *   [0] A scatter (zero fill + placement), [1] external (descendant)
- *   updates, [2] off-diagonal triangular solves, [3] internal updates.
+ *   updates, [2] off-diagonal triangular solves and the diagonal-block
+ *   inverses, [3] internal updates.
  * algorithmic_flops[k] is the arithmetic each kind performs by the
  * method's count (lower-triangle products only), from the analysis.
  * Arrays hold SYM_PROFILE_KINDS entries.  Errors: SYM_EINVAL, SYM_ESTATE,

@@ -696,13 +696,14 @@ int sym_profile(sym_handle h, int enable)
     if (!h) return SYM_EINVAL;
     h->profiling = enable != 0;
     if (h->profiling) {
-        const size_t need = 2 * (h->P.phases.size() + 1);
+        // brackets: the scatter, every phase, the diagonal inverses
+        const size_t need = 2 * (h->P.phases.size() + 2);
         while (h->prof.ev.size() < need) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return SYM_EHIP;
             h->prof.ev.push_back(e);
         }
-        h->prof.kind.assign(h->P.phases.size() + 1, 0);
+        h->prof.kind.assign(h->P.phases.size() + 2, 0);
         h->prof.used = 0;
     }
     return SYM_OK;
