@@ -46,10 +46,104 @@ def cpu_baseline(m: int = 48):
     t0 = time.perf_counter()
     f = oracle.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
     dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(f["flops"] / dt / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
             "kind": "oracle",
             "sample": f"column Cholesky of the same 3-D 7-point recipe on a {m}^3 grid "
-                      f"(n={w.n}, {f['flops']:.3e} flops, geometric ND), {dt:.1f} s"}
+                      f"(n={w.n}, {f['flops']:.3e} flops, geometric ND), {dt:.1f} s",
+            "host_cpu": cpu, "host_threads": os.cpu_count()}
+
+
+def attainable_factor_ms(an, w) -> float:
+    """Sum over supernodes of max(flops / FP64 peak, compulsory bytes / HBM
+    bandwidth): flops = sum of c_j^2 over its columns; bytes = its L
+    entries and A entries (8 B each) and its row indices (4 B each)."""
+    import numpy as np
+    sptr = an.get("super").astype(np.int64)
+    cc = an.get("colcount").astype(np.float64)
+    pinv = np.empty(w.n, np.int64)
+    pinv[an.get("perm").astype(np.int64)] = np.arange(w.n)
+    cols = np.repeat(np.arange(w.n), np.diff(w.Ap))
+    pc = np.minimum(pinv[w.Ai.astype(np.int64)], pinv[cols])
+    a_per_col = np.bincount(pc, minlength=w.n).astype(np.float64)
+    seg = sptr[:-1]
+    flops = np.add.reduceat(cc * cc, seg)
+    lent = np.add.reduceat(cc, seg)
+    aent = np.add.reduceat(a_per_col, seg)
+    rows = cc[seg]
+    nbytes = 8.0 * lent + 8.0 * aent + 4.0 * rows
+    t = np.maximum(flops / (FP64_PEAK_TFLOPS * 1e12), nbytes / (HBM_PEAK_GBPS * 1e9))
+    return float(t.sum() * 1e3)
+
+
+def cold_sweep_ms(torch, an, b, ys, reps: int = 5) -> float:
+    """Forward sweep with L2 and the Infinity Cache evicted first (a 1 GiB
+    device copy before each timed run); median."""
+    import numpy as np
+    src = torch.empty(1 << 27, dtype=torch.float64, device=b.device)
+    dst = torch.empty_like(src)
+    out = []
+    for _ in range(reps):
+        dst.copy_(src)
+        e0, e1 = _events(torch)
+        e0.record()
+        an.solve_lower(b, out=ys)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    del src, dst
+    return float(np.median(out))
+
+
+def small_case(dev, reps: int = 10):
+    """The 64 x 64 2-D 5-point case (n = 4096): latency, not bandwidth, bounds
+    it (L is 0.8 MB and stays in cache); medians in microseconds."""
+    import numpy as np
+    import torch
+
+    import paper_1705_06575_amd as S
+    import workloads as W
+    w = W.config1()
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm)
+    an.bind(dev)
+    rng = np.random.default_rng(20260001)
+    Ax = torch.from_numpy(w.Ax).to(dev)
+    b = torch.from_numpy(W.dense_rhs(w.n, rng)).to(dev)
+    pos, val = W.sparse_rhs(w.n, 8, rng)
+    rp = an.rhs_analyze(pos).bind(dev)
+    bv = torch.from_numpy(val).to(dev)
+    x = torch.empty_like(b)
+    ys = torch.empty_like(b)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            e0, e1 = _events(torch)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1) * 1e3)
+        return round(float(np.median(out)), 1)
+
+    res = {"workload": f"laplace2d_5pt_64x64 (n={w.n}, nnz(L)={int(an.stat('nnzL'))})",
+           "factor_us": timed(lambda: an.factor(Ax)),
+           "fwd_dense_us": timed(lambda: an.solve_lower(b, out=ys)),
+           "full_solve_us": timed(lambda: (x.copy_(b), an.solve_(x))),
+           "fwd_sparse_8_us": timed(lambda: an.solve_lower_sparse(rp, bv, out=ys)),
+           "note": "latency-bound (L cache-resident); no bandwidth fraction reported"}
+    assert an.status() == 0
+    return res
 
 
 def mixed_ir(dev, m: int = 80, reps: int = 3):
@@ -416,6 +510,8 @@ def main():
     t_fwd = timed(lambda: an.solve_lower(b, out=ys), reps)
     t_solve = timed(lambda: (x.copy_(b), an.solve_(x)), reps)
     t_sparse = timed(lambda: an.solve_lower_sparse(rp, bv, out=ys), reps)
+    t_fwd_cold = cold_sweep_ms(torch, an, b, ys)
+    t_attain = attainable_factor_ms(an, w)
 
     # SpTRSV algorithmic bytes (one forward sweep): L's values, each touched
     # block's row indices, and 16 bytes per solved column (read + write of y)
@@ -456,6 +552,10 @@ def main():
         "factor_frac_fp64_peak": round(flops_factor / (t_factor * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
         "sptrsv_fwd_dense_ms": round(t_fwd, 4),
         "sptrsv_fwd_dense_gbps": round(bytes_fwd / (t_fwd * 1e-3) / 1e9, 2),
+        "factor_attainable_ms": round(t_attain, 3),
+        "factor_frac_attainable": round(t_attain / t_factor, 4),
+        "sptrsv_fwd_dense_cold_ms": round(t_fwd_cold, 4),
+        "sptrsv_fwd_dense_cold_gbps": round(bytes_fwd / (t_fwd_cold * 1e-3) / 1e9, 2),
         "sptrsv_fwd_sparse_ms": round(t_sparse, 4),
         "sptrsv_fwd_sparse_gbps": round(bytes_sparse / (t_sparse * 1e-3) / 1e9, 2),
         "full_solve_ms": round(t_solve, 4),
@@ -470,6 +570,7 @@ def main():
                                      "copy-calibrated)",
                      "algorithmic_flops_per_launch": dom_flops_per_launch},
     }
+    out["small_case"] = small_case(dev)
     if not args.no_mixed:
         del an, rp
         torch.cuda.empty_cache()
