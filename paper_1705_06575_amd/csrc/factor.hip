@@ -26,6 +26,9 @@
 //                k-1 is final, every tile of blocks k, k+1, ... subtracts
 //                its product with block k-1 (matrix cores, accumulators
 //                seeded with the tile); tile 0 of block k then factors it.
+//   k_inverse_small / k_inverse_big : after the last level, the inverse of
+//                every diagonal block, stored transposed in the block's
+//                unused upper triangle for the triangular solves.
 // Every tile has exactly one writer per launch and a fixed summation order,
 // so results are bitwise reproducible.  A long external tile is split into
 // parts that run as separate workgroups of the same launch: each stores its

@@ -51,7 +51,7 @@ namespace sym {
 namespace {
 
 constexpr int NT = 256;
-constexpr int LDT = 65;                 // LDS stride of a staged diagonal triangle
+constexpr int LDT = 65;                 // LDS stride of a staged diagonal block
 
 // Stage the upper triangle (diagonal included) of a w x w diagonal block,
 // rows from c0 on, into LDS as doubles (column-major, stride LDT).  The
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
 #pragma unroll
             for (int k = 16; k < 64; ++k) lv[k] = 0.0;
         }
-        __syncthreads();                    // the staged triangle is readable
+        __syncthreads();                    // the staged diagonal block is readable
         const double rd = (tid >= c0 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
         if (tid == 0 && !wait_zero(&pend[tk.J], err)) s_abort = 1;
         __syncthreads();
