@@ -256,13 +256,13 @@ int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algori
  * Per-supernode kernel variants (the choices a cost model makes).  The
  * external update of device supernode s (nds = SYM_STAT_NDSUPER of them)
  * runs its incidences -- (row tile, descendant) products -- either all as
- * per-wavefront items (variant 0) or, for those with at least 32 (variant
- * 1, the default) or 16 (variant 2) rows, columns and inner indices, on
+ * per-wavefront items (variant 0) or, for those with at least 64 (variant
+ * 1, the default) or 32 (variant 2) rows, columns and inner indices, on
  * the whole workgroup through LDS.  Results do not depend on the variant
  * beyond rounding order.  SYM_GET_SUPER_FEAT gives 8 features per device
  * supernode: width, rows, row tiles receiving updates, incidences
  * received, their product flops, the fractions of those flops in
- * incidences of >= 32 and >= 16 rows, columns and inner indices, level.
+ * incidences of >= 64 and >= 32 rows, columns and inner indices, level.
  *
  * sym_set_variants: variant[nds] (values 0..2) for every device supernode;
  * rebuilds the schedule on the host, so the workspace size may change and

@@ -2,7 +2,7 @@
 
 Each device supernode's external update can run in one of three variants
 (sym_set_variants: every incidence on the per-wavefront path, or the ones
-of at least 32 / 16 rows, columns and inner indices on the workgroup's LDS
+of at least 64 / 32 rows, columns and inner indices on the workgroup's LDS
 path; variant 1 is the default).  The autotuner's measurements -- the
 workgroup time of every external-update task of a profiled factorization,
 summed per supernode, under each variant -- train a small network (the

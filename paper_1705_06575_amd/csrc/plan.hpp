@@ -100,9 +100,9 @@ static_assert(sizeof(PartDesc) == 16, "PartDesc layout is shared with the device
 // "large" -- multiplied by the whole workgroup through LDS -- when its
 // product has at least kVariantLarge[v] rows, columns and inner indices;
 // the others run as per-wavefront items.  Variant 0 puts every incidence on
-// the per-wavefront path, 1 (the default) uses 32, 2 uses 16.
+// the per-wavefront path, 1 (the default) uses 64, 2 uses 32.
 constexpr int kVariants = 3;
-constexpr int32_t kVariantLarge[kVariants] = {1 << 30, 32, 16};
+constexpr int32_t kVariantLarge[kVariants] = {1 << 30, 64, 32};
 constexpr int kSuperFeatures = 8;   // features of a device supernode, see Plan::sfeat
 
 // One kernel launch of the factorization.
@@ -209,7 +209,7 @@ struct Plan {
     // per device supernode: kernel variant of its external update, and the
     // features a cost model sees (kSuperFeatures each): width, rows, row
     // tiles of its blocks, incidences it receives, their product flops,
-    // the fractions of those flops in incidences of >= 32 and >= 16 rows,
+    // the fractions of those flops in incidences of >= 64 and >= 32 rows,
     // columns and inner indices, and its level
     std::vector<uint8_t> svariant;
     std::vector<double> sfeat;

@@ -300,8 +300,8 @@ void build_schedule(Plan &P)
                         const int32_t mn = std::min(std::min(ri.b1 - ri.b0, ri.a1 - ri.a0), ri.wk);
                         ft[3] += 1.0;
                         ft[4] += fl;
-                        if (mn >= 32) ft[5] += fl;
-                        if (mn >= 16) ft[6] += fl;
+                        if (mn >= 64) ft[5] += fl;
+                        if (mn >= 32) ft[6] += fl;
                     }
                     small.clear();
                     for (const RawInc &ri : incs_t) {
