@@ -86,7 +86,13 @@ constexpr int32_t kFuseFactor = 1;
 // last adds all partials in part order to the tile (and factors it if the
 // tile carries kFuseFactor).
 constexpr int32_t kPartial = 2;
-constexpr double kSplitUnits = 96.0;   // a tile's estimated 16-wide k-batches per part
+// A part holds about max(kSplitUnits, level cost / kSplitShare) estimated
+// 16-wide k-batches: small levels split finely, so that their few long
+// tiles spread over the chip; large levels split only where a tile would
+// hold a workgroup far beyond the average share (12288 = 256 compute units
+// x 3 resident workgroups x 16).
+constexpr double kSplitUnits = 64.0;
+constexpr double kSplitShare = 12288.0;
 
 struct PartDesc {       // 16 bytes, device-visible
     int32_t counter;    // arrival counter of the split tile (zero between launches)

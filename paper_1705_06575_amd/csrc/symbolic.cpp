@@ -258,15 +258,18 @@ void build_schedule(Plan &P)
         // last wave of workgroups (ties keep the block order)
         std::stable_sort(pending.begin(), pending.end(),
                          [](const Pending &a, const Pending &b) { return a.cost > b.cost; });
-        // a long tile becomes parts of about kSplitUnits each, contiguous
+        // a long tile becomes parts of about one split unit each, contiguous
         // in its incidence list; counters and partial-sum slots are per
         // launch, so every level reuses them from the start
         int32_t lv_counters = 0;
         int64_t lv_slots = 0;
+        double lv_cost = 0.0;
+        for (const Pending &pd : pending) lv_cost += pd.cost;
+        const double unit = std::max(kSplitUnits, lv_cost / kSplitShare);
         for (const Pending &pd : pending) {
             int32_t np = 1;
-            if (pd.cost > kSplitUnits)
-                np = std::min<int32_t>((int32_t)std::ceil(pd.cost / kSplitUnits), (int32_t)pd.incs.size());
+            if (pd.cost > unit)
+                np = std::min<int32_t>((int32_t)std::ceil(pd.cost / unit), (int32_t)pd.incs.size());
             std::vector<size_t> cut(1, 0);
             if (np > 1) {
                 double acc = 0.0;
