@@ -398,7 +398,9 @@ def costmodel(dev, nv: int = 20000, train=(0, 1), held_out: int = 2, reps: int =
     return {"workload": f"knn13 graphs, {nv} vertices x 3 dofs (n={w.n}); train on instances {list(train)}, "
                         f"held-out instance {held_out}",
             "supernodes": nds, "train_rows": int(nrows), "train_loss": round(hist[-1], 4),
-            "train_s": round(train_s, 2), "variants_chosen": np.bincount(choice, minlength=3).tolist(),
+            "train_s": round(train_s, 2),
+            "margin": model.margin if np.isfinite(model.margin) else "none (validation kept the default)",
+            "variants_chosen": np.bincount(choice, minlength=3).tolist(),
             "scored_wg_us": {kk: round(v, 1) for kk, v in scored.items()},
             "share_of_exhaustive_gain": round((scored["default"] - scored["mlp"]) / gain, 3) if gain > 0 else None,
             "factor_ms": {"default": factor_ms(np.ones(nds)), "mlp": factor_ms(choice),
@@ -416,6 +418,7 @@ def main():
     ap.add_argument("--mixed-m", type=int, default=80, help="grid side of the mixed-precision workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched graph workload")
     ap.add_argument("--no-costmodel", action="store_true", help="skip the learned cost model")
+    ap.add_argument("--no-small-case", action="store_true", help="skip the small latency-bound case")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (byte-counter calibration)")
     ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -570,7 +573,8 @@ def main():
                                      "copy-calibrated)",
                      "algorithmic_flops_per_launch": dom_flops_per_launch},
     }
-    out["small_case"] = small_case(dev)
+    if not args.no_small_case:
+        out["small_case"] = small_case(dev)
     if not args.no_mixed:
         del an, rp
         torch.cuda.empty_cache()

@@ -5,16 +5,17 @@ Each device supernode's external update can run in one of three variants
 of at least 64 / 32 rows, columns and inner indices on the workgroup's LDS
 path; variant 1 is the default).  The autotuner's measurements -- the
 workgroup time of every external-update task of a profiled factorization,
-summed per supernode, under each variant -- train a small network (the
+summed per supernode, under each variant -- train small networks (the
 library's FP32 2 x 64 MLP, trained on the GPU by its own forward, backward
-and Adam kernels) to predict, from a supernode's features and a variant
-v != 1, log(T_v / T_1): how much faster or slower v is than the default.
+and Adam kernels; four from different initial weights, averaged) to
+predict, from a supernode's features and a variant v != 1, log(T_v / T_1): how much faster or slower v is than the default.
 The ratio rather than the time itself is learned because the choice
 depends only on differences between variants, which are small next to
 the times.  Supernodes whose default time is below `min_us` are left out
 of training (their ratios are mostly noise and their share of the time
 negligible) and keep the default; a variant replaces the default only
-when its predicted gain exceeds `margin`.  Exhaustive measurement of all
+when its predicted gain exceeds a margin chosen by leave-one-pattern-out
+validation on the training patterns (none, when no margin pays there).  Exhaustive measurement of all
 variants stays the fallback and the judge: `regret` compares a choice with
 the per-supernode best.
 
@@ -74,7 +75,30 @@ def measure_variants(an, Ax, reps: int = 2) -> np.ndarray:
     return T
 
 
-class CostModel:
+class _Chooser:
+    """Variant choice from predicted log-ratios (needs `predict` and
+    `margin`)."""
+
+    def choose(self, feat, margin: float | None = None, min_work: float = 0.0) -> np.ndarray:
+        """Per supernode: the variant with the smallest predicted log-ratio
+        to the default, if that beats the default by more than `margin`
+        (log scale; the model's own, set by `train`, when None), else the
+        default.  Supernodes with fewer than `min_work` update flops keep
+        the default."""
+        if margin is None:
+            margin = self.margin
+        f = np.asarray(feat).reshape(-1, NFEAT)
+        k = f.shape[0]
+        r = np.zeros((k, NVAR))
+        for v in (0, 2):
+            r[:, v] = self.predict(encode(f, np.full(k, v)))
+        v = np.argmin(r, axis=1)
+        keep = (r[np.arange(k), v] > -margin) | (f[:, 4] < min_work)
+        v[keep] = 1
+        return v.astype(np.uint8)
+
+
+class CostModel(_Chooser):
     """The network plus the input standardization it was fit with.
     Targets are log-ratios of a variant's time to the default's."""
 
@@ -96,6 +120,7 @@ class CostModel:
         self.params = torch.from_numpy(p).to(device)
         self.mu = np.zeros(D_IN)
         self.sd = np.ones(D_IN)
+        self.margin = 0.02
 
     def _inputs(self, X):
         import torch
@@ -142,33 +167,70 @@ class CostModel:
                 hist.append(float(np.mean((y - np.asarray(t)) ** 2)))
         return hist
 
-    def choose(self, feat, margin: float = 0.02, min_work: float = 0.0) -> np.ndarray:
-        """Per supernode: the variant with the smallest predicted log-ratio
-        to the default, if that beats the default by more than `margin`
-        (log scale), else the default.  Supernodes with fewer than
-        `min_work` update flops keep the default."""
-        f = np.asarray(feat).reshape(-1, NFEAT)
-        k = f.shape[0]
-        r = np.zeros((k, NVAR))
-        for v in (0, 2):
-            r[:, v] = self.predict(encode(f, np.full(k, v)))
-        v = np.argmin(r, axis=1)
-        keep = (r[np.arange(k), v] > -margin) | (f[:, 4] < min_work)
-        v[keep] = 1
-        return v.astype(np.uint8)
+MARGINS = (0.02, 0.05, 0.1, 0.2)
 
 
-def train(measured, min_us: float = 10.0, epochs: int = 400, seed: int = 0):
-    """A model fit to [(features, T), ...] measured on training patterns,
-    and the update-flop floor below which its choices keep the default
-    (the 5th percentile of the training supernodes')."""
+class Ensemble(_Chooser):
+    """Networks fit from different initial weights to the same rows; the
+    prediction is their mean, which is steadier than any one of them."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        self.margin = 0.02
+
+    def predict(self, X) -> np.ndarray:
+        return np.mean([m.predict(X) for m in self.members], axis=0)
+
+
+MEMBERS = 4
+
+
+def _fit(measured, min_us: float, epochs: int, seed: int, members: int = MEMBERS):
     X = np.concatenate([dataset(f, T, min_us)[0] for f, T in measured])
     t = np.concatenate([dataset(f, T, min_us)[1] for f, T in measured])
     flops = np.concatenate([np.asarray(f).reshape(-1, NFEAT)[np.asarray(T)[:, 1] >= min_us, 4]
                             for f, T in measured])
-    model = CostModel(seed=seed)
-    hist = model.fit(X, t, epochs=epochs)
-    return model, float(np.percentile(flops, 5)), hist, X.shape[0]
+    nets, hist = [], []
+    for i in range(members):
+        net = CostModel(seed=seed + i)
+        hist.append(net.fit(X, t, epochs=epochs))
+        nets.append(net)
+    hist = np.mean(np.asarray(hist), axis=0).tolist()
+    return Ensemble(nets), float(np.percentile(flops, 5)), hist, X.shape[0]
+
+
+def select_margin(measured, min_us: float = 10.0, epochs: int = 400, seed: int = 0,
+                  margins=MARGINS) -> float:
+    """The decision margin by leave-one-pattern-out validation: for each
+    training pattern, a model fit to the others chooses its variants under
+    every candidate margin, scored by that pattern's measured times.  The
+    margin with the smallest summed time wins; if none beats the default
+    variant everywhere (summed over the patterns), the result is infinite,
+    i.e. the model never overrides the default."""
+    cost = np.zeros(len(margins))
+    base = 0.0
+    for i, (f, T) in enumerate(measured):
+        rest = [m for j, m in enumerate(measured) if j != i]
+        model, min_work, _, _ = _fit(rest, min_us, epochs, seed)
+        T = np.asarray(T)
+        k = np.arange(T.shape[0])
+        base += float(T[:, 1].sum())
+        for c, mg in enumerate(margins):
+            cost[c] += float(T[k, model.choose(f, margin=mg, min_work=min_work)].sum())
+    best = int(np.argmin(cost))
+    return float(margins[best]) if cost[best] < base else float("inf")
+
+
+def train(measured, min_us: float = 10.0, epochs: int = 400, seed: int = 0):
+    """An ensemble of MEMBERS networks fit to [(features, T), ...]
+    measured on training patterns, and the update-flop floor below which
+    its choices keep the default (the 5th percentile of the training
+    supernodes').  With two or more patterns the decision margin comes
+    from `select_margin`."""
+    model, min_work, hist, rows = _fit(measured, min_us, epochs, seed)
+    if len(measured) >= 2:
+        model.margin = select_margin(measured, min_us, epochs, seed)
+    return model, min_work, hist, rows
 
 
 def dataset(feat, T, min_us: float = 10.0):

@@ -125,5 +125,5 @@ def test_learned_choice_on_held_out_pattern(torch_cuda):
     share = (default - mlp) / (default - exh) if default > exh else 0.0
     _say(f"case learned choice: {ns} training rows, loss {hist[-1]:.4f}; scored: mlp {mlp:.0f} us, "
          f"default {default:.0f} us, exhaustive {exh:.0f} us (share of the exhaustive gain {share:.2f}); "
-         f"variants used {np.bincount(choice, minlength=3)}")
+         f"variants used {np.bincount(choice, minlength=3)}, margin {model.margin}")
     assert mlp <= 1.005 * default
