@@ -8,16 +8,18 @@ workgroup time of every external-update task of a profiled factorization,
 summed per supernode, under each variant -- train small networks (the
 library's FP32 2 x 64 MLP, trained on the GPU by its own forward, backward
 and Adam kernels; four from different initial weights, averaged) to
-predict, from a supernode's features and a variant v != 1, log(T_v / T_1): how much faster or slower v is than the default.
-The ratio rather than the time itself is learned because the choice
-depends only on differences between variants, which are small next to
-the times.  Supernodes whose default time is below `min_us` are left out
-of training (their ratios are mostly noise and their share of the time
-negligible) and keep the default; a variant replaces the default only
-when its predicted gain exceeds a margin chosen by leave-one-pattern-out
-validation on the training patterns (none, when no margin pays there).  Exhaustive measurement of all
-variants stays the fallback and the judge: `regret` compares a choice with
-the per-supernode best.
+predict, from a supernode's features and a variant v != 1,
+log(T_v / T_1): how much faster or slower v is than the default.  The
+ratio rather than the time itself is learned because the choice depends
+only on differences between variants, which are small next to the times.
+Supernodes whose default time is below `min_us` are left out of training
+(their ratios are mostly noise and their share of the time negligible)
+and keep the default; a variant replaces the default only when its
+predicted gain exceeds a margin chosen by leave-one-pattern-out
+validation on the training patterns (no replacement at all when no
+margin pays there).  Exhaustive measurement of all variants stays the
+fallback and the judge: `regret` compares a choice with the per-supernode
+best.
 
 Argument marshalling only: the network's arithmetic runs in the library's
 kernels (sym_mlp_forward / sym_mlp_backward / sym_mlp_adam).
@@ -204,9 +206,9 @@ def select_margin(measured, min_us: float = 10.0, epochs: int = 400, seed: int =
     """The decision margin by leave-one-pattern-out validation: for each
     training pattern, a model fit to the others chooses its variants under
     every candidate margin, scored by that pattern's measured times.  The
-    margin with the smallest summed time wins; if none beats the default
-    variant everywhere (summed over the patterns), the result is infinite,
-    i.e. the model never overrides the default."""
+    margin with the smallest time summed over the patterns wins; if even
+    that one is not below the default variant's sum, the result is
+    infinite, i.e. the model never overrides the default."""
     cost = np.zeros(len(margins))
     base = 0.0
     for i, (f, T) in enumerate(measured):
