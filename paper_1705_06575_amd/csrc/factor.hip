@@ -264,18 +264,19 @@ __device__ __forceinline__ float lane_value(float v, int src)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-// Reciprocal square root of a pivot: the hardware estimate refined by two
-// Newton steps y <- y + y (1 - d y^2) / 2 (a few ulp; a non-positive or NaN
-// pivot gives NaN or infinity, and the pivot check reports it).
+// Reciprocal square root of a pivot: the hardware estimate (about 24
+// correct bits) refined by one third-order step of the series of
+// (1 - e)^(-1/2), y <- y (1 + e/2 + 3 e^2/8) with e = 1 - d y^2: the
+// truncation is O(e^3), far below rounding, so the result is within about
+// one ulp, as after two Newton steps, with four dependent operations
+// instead of six (it sits on the factorization's critical chain).  A
+// non-positive or NaN pivot gives NaN or infinity, and the pivot check
+// reports it.
 __device__ __forceinline__ double pivot_rsqrt(double d)
 {
-    double y = __builtin_amdgcn_rsq(d);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-d * y, y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
+    const double y = __builtin_amdgcn_rsq(d);
+    const double e = fma(-d * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
 }
 __device__ __forceinline__ float pivot_rsqrt(float d)
 {
@@ -288,8 +289,11 @@ __device__ __forceinline__ float pivot_rsqrt(float d)
 // (LDS, column-major, stride LDC) in place: lane i holds row c0 + i in
 // registers.  Column k: the pivot's reciprocal square root r scales the
 // whole column (the diagonal entry d becomes d r), then the later columns
-// take the rank-1 update with the multipliers read across lanes (no
-// barriers).  Rows c0 .. c0 + wb - 1 form the diagonal block (Cholesky);
+// take the rank-1 update (no barriers): the multiplier of column k + 1,
+// which the next pivot waits for, is read across lanes; the others are
+// broadcast through LDS (every lane stores its entry, with no branch, and
+// reads the ones it needs), which keeps the cross-lane reads (two per
+// value) off the issue path.  Rows c0 .. c0 + wb - 1 form the diagonal block (Cholesky);
 // the rows below get the triangular solve against it.  No lane masks: the
 // entries above the diagonal receive harmless updates (they are stored and
 // never read).  Columns past wb start at zero, never feed the real ones
@@ -298,6 +302,7 @@ template <typename T>
 __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
                                               int32_t *info)
 {
+    __shared__ double bcast[64];
     const int lane = threadIdx.x & 63;
     const int row = c0 + lane;
     const bool mine = row < nr;
@@ -313,8 +318,15 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
         const double d = lane_value(r[k], k);
         bad = (k < wb && !(d > 0.0)) ? min(bad, col0 + c0 + k) : bad;
         r[k] *= pivot_rsqrt(d);
+        if (k + 1 < 16) r[k + 1] = fma(-r[k], lane_value(r[k], k + 1), r[k + 1]);
+        if (k + 2 < 16) {
+            bcast[lane] = r[k];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-        for (int c = k + 1; c < 16; ++c) r[c] = fma(-r[k], lane_value(r[k], c), r[c]);
+            for (int c = k + 2; c < 16; ++c) r[c] = fma(-r[k], bcast[c], r[c]);
+            // the words are read before the next column overwrites them
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
     }
     if (bad != INT_MAX && lane == 0) atomicMin(info, bad);
 #pragma unroll
