@@ -71,6 +71,11 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OSError(f"{path} not found: build it with paper_1705_06575_amd/build.py")
+    # the library runs on PyTorch's HIP runtime: PyTorch is loaded first, so
+    # that the library's HIP dependency resolves to the runtime already in
+    # the process (loaded the other way round, the process holds a second
+    # runtime, which sees no device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
     L.sym_opts_default.restype = None

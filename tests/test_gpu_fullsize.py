@@ -1,0 +1,109 @@
+"""GPU: the mixed-precision and batched workloads at their full sizes, in
+the launch configuration the benchmark times, gated on properties that
+hold at any size (the oracle cannot factor them within the test's time):
+a normwise backward error eta_inf <= 1e-12 evaluated by the oracle from
+A, x and b (on every instance for the single system, on sampled instances
+for the batch), and clean status words."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_1705_06575_amd as S
+    S.load_library()
+    return S
+
+
+@pytest.fixture(scope="module")
+def grid80():
+    return W.config3(80)
+
+
+@pytest.mark.parametrize("precision,method", [("f64", "ir"), ("f32", "pcg")])
+def test_config3_full_size_refinement(S, orc, torch_cuda, grid80, precision, method):
+    """3-D 27-point weighted Laplacian on 80^3 (n = 512000, kappa ~ 1e6):
+    FP64 factor, or FP32 factor with conjugate-gradient refinement, to
+    eta_inf <= 1e-12."""
+    torch = torch_cuda
+    w = grid80
+    _say(f"case config3 full size {precision} {method}: n {w.n}")
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision=precision)
+    Ax = torch.from_numpy(w.Ax).cuda()
+    an.factor(Ax)
+    assert an.status() == 0
+    b = W.dense_rhs(w.n, np.random.default_rng(11))
+    x, iters, eta = an.refine(Ax, torch.from_numpy(b).cuda(), tol=1e-12, maxit=30, method=method)
+    eta_orc = orc.eta_inf(w.n, w.Ap, w.Ai, w.Ax, x.cpu().numpy(), b)
+    _say(f"case config3 full size {precision} {method}: iters {iters} eta {eta:.2e} (oracle {eta_orc:.2e})")
+    assert eta <= 1e-12 and eta_orc <= 1e-12
+    assert iters <= (1 if precision == "f64" else 10)
+
+
+def test_config4_full_batch_in_one_graph(S, orc, torch_cuda):
+    """512 instances of the 2-D 9-point 128^2 pattern and 64 each of the
+    3-D 7-point 24^3 and 40^3 patterns: FP32 factors and four FP64
+    refinement steps for all of them captured in one HIP graph, replayed
+    twice with eager work between the replays; after each replay every
+    status word is clean, and sampled instances reach eta_inf <= 1e-12 by
+    the oracle's evaluation."""
+    torch = torch_cuda
+    groups = []
+    for kind, m in (("9pt128", 512), ("7pt24", 64), ("7pt40", 64)):
+        n, Ap, Ai, X, perm = W.config4_batch(kind, m)
+        an = S.Analysis(n, Ap, Ai, ordering=perm, precision="f32")
+        an.bind(torch.device("cuda"))
+        bt = S.Batch(an, m)
+        B = np.random.default_rng(20261000).uniform(-1.0, 1.0, (m, n))
+        groups.append(dict(kind=kind, m=m, n=n, Ap=Ap, Ai=Ai, Xh=X, an=an, bt=bt,
+                           vals=torch.from_numpy(X).cuda(), Bh=B, B=torch.from_numpy(B).cuda()))
+        groups[-1]["X"] = torch.empty_like(groups[-1]["B"])
+        _say(f"case config4 group {kind}: {m} instances, n {n}")
+
+    def run():
+        for g in groups:
+            g["bt"].factor(g["vals"])
+            g["bt"].refine(g["vals"], g["B"], g["X"], 4)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    for rep in range(2):
+        for g in groups:
+            g["X"].zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for g in groups:
+            assert (g["bt"].status() == 0).all()
+            Xh = g["X"].cpu().numpy()
+            for k in sorted({0, g["m"] // 2, g["m"] - 1}):
+                eta = orc.eta_inf(g["n"], g["Ap"], g["Ai"], g["Xh"][k], Xh[k], g["Bh"][k])
+                _say(f"case config4 replay {rep} {g['kind']} instance {k}: eta {eta:.2e}")
+                assert eta <= 1e-12
+    del graph
