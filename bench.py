@@ -196,9 +196,10 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
     return out
 
 
-# the factor kernels and the schedule they run (tasks, splits, items)
+# the factor kernels, the schedule they run (tasks, splits, items) and the
+# ordering and defaults that shape it
 FACTOR_SOURCES = [os.path.join(ROOT, "paper_1705_06575_amd", "csrc", f)
-                  for f in ("factor.hip", "symbolic.cpp", "plan.hpp")]
+                  for f in ("factor.hip", "symbolic.cpp", "plan.hpp", "ordering.cpp", "capi.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_factor_grid3d_7pt_64.json")
 FACTOR_KERNELS = ("k_external", "k_internal", "k_trsm")
 

@@ -57,7 +57,7 @@ typedef struct sym_opts {
     const int32_t *perm;     /* host int32[n], perm[new] = old, for SYM_ORDER_USER */
     int32_t block_width;     /* widest column block a device task handles (default 64; 16..64, multiple of 16) */
     int32_t precision;       /* SYM_F64 (default) or SYM_F32: storage and arithmetic of L */
-    int32_t nd_leaf;         /* SYM_ORDER_ND: subgraphs up to this size are not split further (default 64) */
+    int32_t nd_leaf;         /* SYM_ORDER_ND: subgraphs up to this size are not split further (default 24) */
     int32_t amalgamate;      /* 1 (default): merge small supernodes into device panels with explicit
                                 zeros; 0: device panels are the fundamental supernodes.  Reported
                                 symbolic outputs are the fundamental ones either way. */

@@ -173,7 +173,7 @@ class Analysis:
     an int32 permutation array perm[new] = old.
     """
 
-    def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=64,
+    def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=24,
                  amalgamate=True):
         L = load_library()
         self._lib = L

@@ -118,7 +118,7 @@ void sym_opts_default(sym_opts *o)
     o->perm = nullptr;
     o->block_width = 64;
     o->precision = SYM_F64;
-    o->nd_leaf = 64;
+    o->nd_leaf = 24;
     o->amalgamate = 1;
 }
 
@@ -137,7 +137,7 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
     try {
         h->P.precision = o.precision;
         rc = sym::analyze(n, Ap, Ai, o.ordering, o.perm, o.block_width ? o.block_width : 64,
-                          o.nd_leaf > 0 ? o.nd_leaf : 64, o.amalgamate != 0, h->P);
+                          o.nd_leaf > 0 ? o.nd_leaf : 24, o.amalgamate != 0, h->P);
         if (rc == SYM_OK) layout(h);
     } catch (const std::bad_alloc &) {
         rc = SYM_ENOMEM;
