@@ -42,6 +42,8 @@ extern "C" {
 #define SYM_ESTATE (-5)     /* call out of order: e.g. factor before bind, solve before factor */
 #define SYM_EWORKSPACE (-6) /* workspace too small or misaligned */
 #define SYM_ESCHED (-7)     /* a device scheduler gave up waiting (internal error) */
+#define SYM_ENUMERIC (-8)   /* refinement on a failed factor (a non-positive pivot), or its
+                               backward error is not finite (NaN or infinity) */
 
 /* orderings */
 #define SYM_ORDER_ND 0      /* the library's own graph nested dissection */
@@ -140,8 +142,10 @@ int sym_solve_upper(sym_handle h, double *y_dev, void *stream);
  * maxit corrections, else x += solve(r).  b_dev, x_dev: device double[n],
  * original ordering, distinct.  Synchronizes the stream once per iteration
  * to read eta.  *iters (may be NULL): corrections applied; *eta (may be
- * NULL): final backward error (NaN if the factor failed).  Errors:
- * SYM_EINVAL, SYM_ESTATE (no factor), SYM_EHIP.
+ * NULL): final backward error.  A NaN anywhere in r or x makes eta NaN.
+ * Errors: SYM_EINVAL, SYM_ESTATE (no factor), SYM_EHIP, SYM_ENUMERIC (the
+ * factor recorded a non-positive pivot, or eta is not finite; *iters and
+ * *eta still hold what was reached).
  */
 int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *x_dev, double tol,
                int32_t maxit, void *stream, int32_t *iters, double *eta);
@@ -318,7 +322,10 @@ int sym_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *
  * can be captured into a HIP graph and replayed.
  *
  * sym_batch_create: 1 <= m <= 65535.  sym_batch_bind: h must be bound
- * (SYM_ESTATE otherwise); alignment and size rules as sym_bind.
+ * (SYM_ESTATE otherwise); alignment and size rules as sym_bind.  The batch
+ * holds the analysis's device plan as it was at sym_batch_bind: after a
+ * later sym_bind or sym_set_variants on h every batch call returns
+ * SYM_ESTATE until the batch is bound again.
  * sym_batch_factor: factor all m value sets.  sym_batch_solve: in place,
  * A_i x_i = b_i for every instance.  sym_batch_refine: x_i = solve(b_i)
  * followed by exactly `steps` FP64 refinement steps r = b - A x, x +=

@@ -21,7 +21,7 @@ SYM_F64, SYM_F32 = 0, 1
 
 _ERRORS = {
     -1: "SYM_EINVAL", -2: "SYM_EPATTERN", -3: "SYM_ENOMEM", -4: "SYM_EHIP",
-    -5: "SYM_ESTATE", -6: "SYM_EWORKSPACE", -7: "SYM_ESCHED",
+    -5: "SYM_ESTATE", -6: "SYM_EWORKSPACE", -7: "SYM_ESCHED", -8: "SYM_ENUMERIC",
 }
 
 GET = dict(perm=1, parent=2, colcount=3, Lp=4, Li=5, super=6, sparent=7, blocks=8, blevel=9,

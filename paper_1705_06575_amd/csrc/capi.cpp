@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -26,6 +27,10 @@ struct sym_plan {
     sym::DevicePlan D;
     bool bound = false;
     bool factored = false;
+    // bumped whenever the device plan arrays move or the schedule changes
+    // (sym_bind, sym_set_variants): a batch bound to an older generation
+    // holds stale pointers and sizes and refuses to run
+    uint64_t generation = 0;
     hipStream_t stream = nullptr;
     bool profiling = false;
     sym::FactorProfile prof;
@@ -104,6 +109,25 @@ hipError_t upload(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     if (bytes == 0) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+
+// eta_inf = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) from the residual
+// kernel's maxima cur = {|r|, (unused), |x|, |b|}; NaN stays NaN.
+double backward_error(double anorm, const double cur[4])
+{
+    const double den = anorm * cur[2] + cur[3];
+    return den > 0.0 ? cur[0] / den : cur[0];
+}
+
+// Whether the last factorization recorded a non-positive pivot (its first
+// status word); synchronizes the stream.  False if a HIP call failed.
+bool read_pivot_failed(sym_plan *h, hipStream_t s, bool &failed)
+{
+    int32_t w = INT32_MAX;
+    if (hipMemcpyAsync(&w, h->D.info, sizeof(w), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+    if (hipStreamSynchronize(s) != hipSuccess) return false;
+    failed = w != INT32_MAX;
+    return true;
 }
 
 }  // namespace
@@ -242,6 +266,7 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.arowptr, P.arowptr.data(), sizeof(int64_t) * P.arowptr.size(), s);
     if (e == hipSuccess) e = upload(D.acol, P.acol.data(), sizeof(int32_t) * P.acol.size(), s);
     if (e == hipSuccess) e = upload(D.aval, P.aval.data(), sizeof(int64_t) * P.aval.size(), s);
+    h->generation++;
     if (e != hipSuccess) return SYM_EHIP;
     h->bound = true;
     h->factored = false;
@@ -319,15 +344,16 @@ int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *
     double red[4] = {0, 0, 0, 0};
     double e = 0.0;
     int32_t it = 0;
+    bool pivot_failed = false;
     for (;;) {
         if (sym::launch_residual(P, D, Ax_dev, b_dev, x_dev, D.vec3, it == 0, s) != hipSuccess) return SYM_EHIP;
         double cur[4];
         if (hipMemcpyAsync(cur, D.red, sizeof(cur), hipMemcpyDeviceToHost, s) != hipSuccess) return SYM_EHIP;
+        if (it == 0 && !read_pivot_failed(h, s, pivot_failed)) return SYM_EHIP;
         if (hipStreamSynchronize(s) != hipSuccess) return SYM_EHIP;
         if (it == 0) red[1] = cur[1];
-        const double den = red[1] * cur[2] + cur[3];
-        e = den > 0.0 ? cur[0] / den : cur[0];
-        if (!(e > tol) || it >= maxit) break;      // also stops on NaN
+        e = backward_error(red[1], cur);
+        if (!(e > tol) || it >= maxit || pivot_failed) break;      // also stops on NaN
         rc = sym_solve(h, D.vec3, stream);           // correction, in place
         if (rc != SYM_OK) return rc;
         if (sym::launch_axpy(P, D, x_dev, D.vec3, s) != hipSuccess) return SYM_EHIP;
@@ -335,7 +361,7 @@ int sym_refine(sym_handle h, const double *Ax_dev, const double *b_dev, double *
     }
     if (iters) *iters = it;
     if (eta) *eta = e;
-    return SYM_OK;
+    return (pivot_failed || !std::isfinite(e)) ? SYM_ENUMERIC : SYM_OK;
 }
 
 int sym_set_variants(sym_handle h, const uint8_t *variant, int32_t count)
@@ -352,6 +378,7 @@ int sym_set_variants(sym_handle h, const uint8_t *variant, int32_t count)
     layout(h);
     h->bound = false;
     h->factored = false;
+    h->generation++;
     return SYM_OK;
 }
 
@@ -398,15 +425,16 @@ int sym_refine_pcg(sym_handle h, const double *Ax_dev, const double *b_dev, doub
     if (rc != SYM_OK) return rc;
     double anorm = 0.0, e = 0.0, rho = 0.0;
     int32_t it = 0;
+    bool pivot_failed = false;
     for (;;) {
         // true residual and its backward error
         if (sym::launch_residual(P, D, Ax_dev, b_dev, x_dev, r, it == 0, s) != hipSuccess) return SYM_EHIP;
         double cur[4];
+        if (it == 0 && !read_pivot_failed(h, s, pivot_failed)) return SYM_EHIP;
         if (!fetch(D.red, cur, 4)) return SYM_EHIP;
         if (it == 0) anorm = cur[1];
-        const double den = anorm * cur[2] + cur[3];
-        e = den > 0.0 ? cur[0] / den : cur[0];
-        if (!(e > tol) || it >= maxit) break;      // also stops on NaN
+        e = backward_error(anorm, cur);
+        if (!(e > tol) || it >= maxit || pivot_failed) break;      // also stops on NaN
         // z = M r, rho' = r . z, p = z + (rho' / rho) p
         if (hipMemcpyAsync(z, r, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SYM_EHIP;
         rc = sym_solve(h, z, stream);
@@ -431,7 +459,7 @@ int sym_refine_pcg(sym_handle h, const double *Ax_dev, const double *b_dev, doub
     }
     if (iters) *iters = it;
     if (eta) *eta = e;
-    return SYM_OK;
+    return (pivot_failed || !std::isfinite(e)) ? SYM_ENUMERIC : SYM_OK;
 }
 
 int sym_rhs_analyze(sym_handle h, int64_t nb, const int32_t *bi, sym_rhs *out)
@@ -778,8 +806,17 @@ struct sym_batch {
            off_red = 0, off_sync = 0, off_pcount = 0, off_pbuf = 0;
     sym::DevicePlan D;              // the analysis's plan arrays, the batch's own buffers
     bool bound = false, factored = false;
+    uint64_t generation = 0;        // the analysis's generation when the batch was bound
     hipStream_t stream = nullptr;
 };
+
+// A batch runs only while the analysis is bound to the same workspace and
+// schedule it copied at its own bind (the plan pointers and the split-tile
+// buffer sizes come from there).
+static bool batch_current(const sym_batch *b)
+{
+    return b->bound && b->h->bound && b->generation == b->h->generation;
+}
 
 int sym_batch_create(sym_handle h, int32_t m, sym_batch_t *out)
 {
@@ -845,13 +882,14 @@ int sym_batch_bind(sym_batch_t b, void *dev_ws, size_t bytes, void *stream)
     b->stream = (hipStream_t)stream;
     b->bound = true;
     b->factored = false;
+    b->generation = b->h->generation;
     return SYM_OK;
 }
 
 int sym_batch_factor(sym_batch_t b, const double *Ax_dev, void *stream)
 {
     if (!b || (!Ax_dev && b->h->P.nnzA)) return SYM_EINVAL;
-    if (!b->bound || !b->h->bound) return SYM_ESTATE;
+    if (!batch_current(b)) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     b->stream = s;
     if (sym::launch_factor(b->h->P, b->D, Ax_dev, s, nullptr) != hipSuccess) return SYM_EHIP;
@@ -862,7 +900,7 @@ int sym_batch_factor(sym_batch_t b, const double *Ax_dev, void *stream)
 int sym_batch_solve(sym_batch_t b, double *bx_dev, void *stream)
 {
     if (!b || (!bx_dev && b->h->P.n)) return SYM_EINVAL;
-    if (!b->bound || !b->factored) return SYM_ESTATE;
+    if (!batch_current(b) || !b->factored) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     b->stream = s;
     const sym::Plan &P = b->h->P;
@@ -879,7 +917,7 @@ int sym_batch_refine(sym_batch_t b, const double *Ax_dev, const double *b_dev, d
                      int32_t steps, void *stream)
 {
     if (!b || ((!Ax_dev || !b_dev || !x_dev) && b->h->P.n) || steps < 0) return SYM_EINVAL;
-    if (!b->bound || !b->factored) return SYM_ESTATE;
+    if (!batch_current(b) || !b->factored) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     const sym::Plan &P = b->h->P;
     const sym::DevicePlan &D = b->D;
@@ -901,7 +939,7 @@ int sym_batch_eta(sym_batch_t b, const double *Ax_dev, const double *b_dev, cons
                   double *eta_host, void *stream)
 {
     if (!b || !eta_host || ((!Ax_dev || !b_dev || !x_dev) && b->h->P.n)) return SYM_EINVAL;
-    if (!b->bound) return SYM_ESTATE;
+    if (!batch_current(b)) return SYM_ESTATE;
     hipStream_t s = (hipStream_t)stream;
     const sym::Plan &P = b->h->P;
     const sym::DevicePlan &D = b->D;
@@ -925,7 +963,7 @@ int sym_batch_eta(sym_batch_t b, const double *Ax_dev, const double *b_dev, cons
 int sym_batch_status(sym_batch_t b, int64_t *info_host)
 {
     if (!b || !info_host) return SYM_EINVAL;
-    if (!b->bound || !b->factored) return SYM_ESTATE;
+    if (!batch_current(b) || !b->factored) return SYM_ESTATE;
     if (hipStreamSynchronize(b->stream) != hipSuccess) return SYM_EHIP;
     std::vector<int32_t> w((size_t)b->m * 4);
     if (hipMemcpy(w.data(), b->D.info, sizeof(int32_t) * w.size(), hipMemcpyDeviceToHost) != hipSuccess)

@@ -9,7 +9,10 @@
 // (built by the analysis from the lower-triangle input), one thread per row,
 // so every entry of r has one writer and a fixed summation order.  The
 // infinity norms are maxima of nonnegative doubles, taken with atomic
-// maxima on their bit patterns (order-independent, so exact).
+// maxima on their bit patterns (order-independent, so exact).  A NaN
+// anywhere (a failed factor fills x with NaN) makes the norm NaN: the
+// maxima keep NaN operands instead of dropping them, so a broken solve can
+// never report a small backward error.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -18,15 +21,25 @@ namespace sym {
 
 namespace {
 
+// max(a, b) that returns NaN when either operand is NaN (fmax would drop it)
+__device__ __forceinline__ double nan_max(double a, double b)
+{
+    return (b > a || b != b) ? b : a;
+}
+
 __device__ __forceinline__ void atomic_max_nonneg(double *addr, double v)
 {
-    // nonnegative IEEE doubles order like their bit patterns as unsigned integers
-    atomicMax((unsigned long long *)addr, (unsigned long long)__double_as_longlong(v));
+    // nonnegative IEEE doubles order like their bit patterns as unsigned
+    // integers, and the positive quiet NaN's pattern lies above +infinity's,
+    // so a NaN (made positive here) wins every later maximum
+    const unsigned long long bits = v != v ? 0x7ff8000000000000ull
+                                           : (unsigned long long)__double_as_longlong(v);
+    atomicMax((unsigned long long *)addr, bits);
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off));
     return v;
 }
 
@@ -61,10 +74,10 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
         }
         const double ri = b[i] - s;
         r[i] = ri;
-        mr = fmax(mr, fabs(ri));
-        ma = fmax(ma, sa);
-        mx = fmax(mx, fabs(x[i]));
-        mb = fmax(mb, fabs(b[i]));
+        mr = nan_max(mr, fabs(ri));
+        ma = nan_max(ma, sa);
+        mx = nan_max(mx, fabs(x[i]));
+        mb = nan_max(mb, fabs(b[i]));
     }
     mr = wave_max(mr);
     ma = wave_max(ma);

@@ -150,3 +150,26 @@ def test_graph_capture_of_uneven_batches(S, torch_cuda):
             assert d <= 1e-12
             assert (eta <= 1e-12).all()
             assert (g["bt"].status() == 0).all()
+
+
+def test_batch_refuses_stale_plan(S, torch_cuda):
+    """After the analysis is rebound (here: new kernel variants, which
+    rebuild its schedule) a batch bound before holds stale device pointers:
+    its calls fail with SYM_ESTATE until it is bound again."""
+    from paper_1705_06575_amd import SymError
+    torch = torch_cuda
+    ws = _instances((12, 12), 2, 500)
+    w0 = ws[0]
+    an = S.Analysis(w0.n, w0.Ap, w0.Ai, ordering="nd")
+    Axb = torch.from_numpy(np.stack([w.Ax for w in ws])).cuda()
+    bt = S.Batch(an, 2)
+    bt.factor(Axb)
+    assert (bt.status() == 0).all()
+    an.set_variants(np.zeros(int(an.stat("ndsuper")), np.uint8))
+    an.bind()
+    with pytest.raises(SymError) as e:
+        bt.factor(Axb)
+    assert e.value.name == "SYM_ESTATE"
+    bt2 = S.Batch(an, 2)
+    bt2.factor(Axb)
+    assert (bt2.status() == 0).all()

@@ -143,3 +143,25 @@ def test_fp32_indefinite_reports_pivot(S, orc, torch_cuda):
     an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision="f32")
     an.factor(torch.from_numpy(Ax).cuda())
     assert an.status() == 1 + int(w.perm[f["info"] - 1])
+
+
+@pytest.mark.parametrize("method", ["ir", "pcg"])
+def test_refinement_on_failed_factor_is_an_error(S, orc, torch_cuda, method):
+    """An indefinite matrix: the FP32 factor records a non-positive pivot and
+    its solves fill x with NaN.  Refinement must not report a small backward
+    error for that: the call fails with SYM_ENUMERIC and eta is not <= tol."""
+    from paper_1705_06575_amd import SymError
+    torch = torch_cuda
+    w = W.random_spd(80, 0.1, np.random.default_rng(78))
+    Ax = w.Ax.copy()
+    col = 21
+    Ax[w.Ap[col]] = -Ax[w.Ap[col]]
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision="f32")
+    Axd = torch.from_numpy(Ax).cuda()
+    an.factor(Axd)
+    assert an.status() != 0
+    b = torch.from_numpy(W.dense_rhs(w.n, np.random.default_rng(5))).cuda()
+    with pytest.raises(SymError) as e:
+        an.refine(Axd, b, tol=1e-12, maxit=5, method=method)
+    _say(f"case refine {method} on failed factor: {e.value.name}")
+    assert e.value.name == "SYM_ENUMERIC"

@@ -167,6 +167,24 @@ def test_state_errors_without_device(S):
     # misaligned workspace
     assert lib.sym_bind(an._h, ctypes.c_void_p(4096 + 8), sz, None) == -6
     assert lib.sym_bind(an._h, ctypes.c_void_p(4096), ctypes.c_size_t(sz.value - 1), None) == -6
+    # a batch on an unbound analysis, or itself unbound, runs nothing
+    b = ctypes.c_void_p()
+    assert lib.sym_batch_create(an._h, 2, ctypes.byref(b)) == 0
+    assert lib.sym_batch_workspace(b, ctypes.byref(sz)) == 0 and sz.value > 0
+    assert lib.sym_batch_bind(b, ctypes.c_void_p(4096), sz, None) == -5
+    p = ctypes.c_void_p(16)
+    assert lib.sym_batch_factor(b, p, None) == -5
+    assert lib.sym_batch_solve(b, p, None) == -5
+    assert lib.sym_batch_refine(b, p, p, ctypes.c_void_p(32), 1, None) == -5
+    eta = np.zeros(2)
+    assert lib.sym_batch_eta(b, p, p, p, eta.ctypes.data_as(ctypes.c_void_p), None) == -5
+    info2 = np.zeros(2, np.int64)
+    assert lib.sym_batch_status(b, info2.ctypes.data_as(ctypes.c_void_p)) == -5
+    lib.sym_batch_destroy(b)
+    # refinement before a factorization
+    it, e = ctypes.c_int32(), ctypes.c_double()
+    assert lib.sym_refine(an._h, p, p, ctypes.c_void_p(32), 1e-12, 5, None,
+                          ctypes.byref(it), ctypes.byref(e)) == -5
 
 
 def test_empty_matrix(S):
