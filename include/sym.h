@@ -121,6 +121,25 @@ int sym_factor(sym_handle h, const double *Ax_dev, void *stream);
 int sym_solve(sym_handle h, double *bx_dev, void *stream);
 
 /*
+ * For callers that cannot allocate device memory or must not touch the
+ * handle's scratch (code under graph capture, serving loops): the full
+ * solve of sym_solve, with the sweeps' scratch -- the accumulator and
+ * forward-result vectors, per-block counters, done flags and ticket word --
+ * taken from a fixed static device array of the library instead of the
+ * bound workspace (which still supplies the plan and the factor).  The
+ * array holds n and block counts up to SYM_STATIC_MAX_N (about 12.6 MB per
+ * GPU, resident from the first call on that GPU until the process ends).
+ * The call allocates nothing.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (other streams, other threads, other
+ * handles) race and give wrong results; serialize them.  Every value it
+ * needs cleared is reset by a kernel at the start of each sweep.  Errors:
+ * SYM_EINVAL, SYM_EWORKSPACE (n or the number of device blocks exceeds
+ * SYM_STATIC_MAX_N), SYM_ESTATE (no factor), SYM_EHIP.
+ */
+#define SYM_STATIC_MAX_N 524288
+int sym_solve_static(sym_handle h, double *bx_dev, void *stream);
+
+/*
  * Forward sweep only: y = L^-1 P b.  b_dev: device double[n] in the
  * original ordering (read only); y_dev: device double[n] in the permuted
  * ordering of L (written).  Errors as sym_solve.

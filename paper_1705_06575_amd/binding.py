@@ -52,7 +52,7 @@ class sym_opts(ctypes.Structure):
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
-           "sym_solve", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
+           "sym_solve", "sym_solve_static", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
            "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
            "sym_export_factor", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
            "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.sym_bind.argtypes = [vp, vp, sz, vp]
     L.sym_factor.argtypes = [vp, vp, vp]
     L.sym_solve.argtypes = [vp, vp, vp]
+    L.sym_solve_static.argtypes = [vp, vp, vp]
     L.sym_solve_lower.argtypes = [vp, vp, vp, vp]
     L.sym_solve_upper.argtypes = [vp, vp, vp]
     L.sym_rhs_analyze.argtypes = [vp, i64, vp, ctypes.POINTER(vp)]
@@ -290,6 +291,13 @@ class Analysis:
 
     def solve_(self, bx):
         _check("sym_solve", self._lib.sym_solve(self._h, _dev_ptr(bx, "torch.float64", self.n), _stream()))
+        return bx
+
+    def solve_static_(self, bx):
+        """In place, as solve_, through sym_solve_static (the sweeps' scratch in
+        the library's static device array; nothing is allocated)."""
+        _check("sym_solve_static", self._lib.sym_solve_static(
+            self._h, _dev_ptr(bx, "torch.float64", self.n), _stream()))
         return bx
 
     def refine(self, Ax, b, tol=1e-12, maxit=20, out=None, method="ir"):

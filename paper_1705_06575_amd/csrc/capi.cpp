@@ -13,6 +13,8 @@
 #include "plan.hpp"
 #include "sym.h"
 
+static_assert(SYM_STATIC_MAX_N == sym::kStaticMaxN, "static scratch bound of the ABI");
+
 struct sym_plan {
     sym::Plan P;
     size_t ws_bytes = 0;
@@ -319,6 +321,32 @@ int sym_solve(sym_handle h, double *bx_dev, void *stream)
     if (sym::launch_fwd(h->P, h->D, acc, y, s) != hipSuccess) return SYM_EHIP;
     if (sym::launch_bwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
     if (sym::launch_perm_scatter(h->P, h->D, y, bx_dev, s) != hipSuccess) return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_solve_static(sym_handle h, double *bx_dev, void *stream)
+{
+    if (!h || (!bx_dev && h->P.n)) return SYM_EINVAL;
+    const sym::Plan &P = h->P;
+    if ((int64_t)P.n > sym::kStaticMaxN || (int64_t)P.nb > sym::kStaticMaxN) return SYM_EWORKSPACE;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    if (P.n == 0) return SYM_OK;
+    void *base = nullptr;
+    if (sym::static_scratch(&base) != hipSuccess) return SYM_EHIP;
+    // the bound plan and factor, with the sweeps' scratch in the static array
+    sym::DevicePlan D = h->D;
+    char *sc = (char *)base;
+    D.vec = (double *)sc;
+    D.vec2 = (double *)(sc + sym::kStaticOffVec2);
+    D.pend = (int32_t *)(sc + sym::kStaticOffPend);
+    D.done = (int32_t *)(sc + sym::kStaticOffDone);
+    D.ticket = (int32_t *)(sc + sym::kStaticOffTicket);
+    if (sym::launch_perm_gather(P, D, bx_dev, D.vec, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_fwd(P, D, D.vec, D.vec2, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_bwd(P, D, D.vec2, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_perm_scatter(P, D, D.vec2, bx_dev, s) != hipSuccess) return SYM_EHIP;
     return SYM_OK;
 }
 

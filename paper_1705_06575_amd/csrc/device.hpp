@@ -84,6 +84,19 @@ hipError_t launch_factor(const Plan &P, const DevicePlan &D, const double *Ax, h
                          FactorProfile *prof);
 
 // ---- solve (solve.hip)
+// Static scratch of the allocation-free full solve: accumulator and forward
+// result (kStaticMaxN doubles each), live counters and done flags
+// (kStaticMaxN int32 each), ticket words (64 bytes).
+constexpr int64_t kStaticMaxN = int64_t(1) << 19;
+constexpr int kStaticMaxDevices = 64;
+constexpr size_t kStaticOffVec2 = 8 * (size_t)kStaticMaxN;
+constexpr size_t kStaticOffPend = 16 * (size_t)kStaticMaxN;
+constexpr size_t kStaticOffDone = 20 * (size_t)kStaticMaxN;
+constexpr size_t kStaticOffTicket = 24 * (size_t)kStaticMaxN;
+constexpr size_t kStaticScratchBytes = kStaticOffTicket + 256;
+// Device address of the scratch on the current GPU (looked up once per
+// device).
+hipError_t static_scratch(void **ptr);
 hipError_t launch_perm_gather(const Plan &P, const DevicePlan &D, const double *b, double *y,
                               hipStream_t s);
 hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double *y, double *x,

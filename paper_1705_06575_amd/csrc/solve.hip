@@ -43,10 +43,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device.hpp"
 
 namespace sym {
+
+// Scratch of the allocation-free full solve: the two n-vectors of the
+// sweeps (accumulator and forward result), the per-block counters and done
+// flags, and the ticket word, for n and block counts up to kStaticMaxN.
+// One copy per GPU, held until the process ends; every call on a GPU
+// shares it.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -505,7 +513,29 @@ hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s
     return hipGetLastError();
 }
 
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kStaticMaxDevices] = {};
+
 }  // namespace
+
+hipError_t static_scratch(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kStaticMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        // the array's name is a host-side stand-in: its device address on
+        // the current GPU comes from the runtime, once per device
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *ptr = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_perm_gather(const Plan &P, const DevicePlan &D, const double *b, double *y,
                               hipStream_t s)

@@ -187,6 +187,21 @@ def test_state_errors_without_device(S):
                           ctypes.byref(it), ctypes.byref(e)) == -5
 
 
+def test_static_solve_rejects_oversized_systems(S):
+    """sym_solve_static's scratch holds n up to SYM_STATIC_MAX_N: larger
+    systems are refused with SYM_EWORKSPACE before any device work."""
+    lib = S.load_library()
+    n = 524288 + 1
+    Ap = np.arange(n + 1, dtype=np.int64)
+    Ai = np.arange(n, dtype=np.int32)
+    an = S.Analysis(n, Ap, Ai, ordering="natural")
+    assert lib.sym_solve_static(an._h, ctypes.c_void_p(256), None) == -6
+    assert lib.sym_solve_static(None, ctypes.c_void_p(256), None) == -1
+    small = W.config1()
+    an2 = S.Analysis(small.n, small.Ap, small.Ai, ordering=small.perm)
+    assert lib.sym_solve_static(an2._h, ctypes.c_void_p(256), None) == -5
+
+
 def test_empty_matrix(S):
     an = S.Analysis(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
     assert an.stat("nnzL") == 0 and an.stat("nblocks") == 0
