@@ -151,7 +151,9 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
     workload (3-D 27-point weighted Laplacian on an m^3 grid, weights
     log-uniform in [1e-3, 1e3], diagonal = row sum * (1 + 1e-6), geometric
     nested dissection): FP64 factor + solve (+ refinement if needed) against
-    FP32 factor + FP64 iterative refinement, both on this GPU."""
+    FP32 factors (FP32 update products, or bfloat16 / IEEE-half update
+    products with per-supernode scaling) + FP64 iterative refinement, all on
+    this GPU."""
     import numpy as np
     import torch
 
@@ -163,12 +165,13 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
     x = torch.empty_like(b)
     out = {"workload": f"grid3d_27pt_{m}^3 weighted Laplacian (n={w.n}), geometric ND",
            "tol": 1e-12}
-    for prec, method in (("f64", "ir"), ("f32", "ir"), ("f32", "pcg")):
+    for prec, method in (("f64", "ir"), ("f32", "ir"), ("f32", "pcg"), ("bf16", "pcg"),
+                         ("f16", "pcg")):
         an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision=prec)
         an.bind(dev)
         flops = an.stat("flops")
         an.factor(Ax)
-        an.refine(Ax, b, tol=1e-12, maxit=50, out=x, method=method)      # warm-up
+        an.refine(Ax, b, tol=1e-12, maxit=200, out=x, method=method)      # warm-up
         torch.cuda.synchronize()
         times, tf = [], []
         for _ in range(reps):
@@ -176,7 +179,7 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
             an.factor(Ax)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            _, iters, eta = an.refine(Ax, b, tol=1e-12, maxit=50, out=x, method=method)
+            _, iters, eta = an.refine(Ax, b, tol=1e-12, maxit=200, out=x, method=method)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             times.append((t2 - t0) * 1e3)
@@ -185,12 +188,13 @@ def mixed_ir(dev, m: int = 80, reps: int = 3):
         key = prec if prec == "f64" else f"{prec}_{method}"
         out[key] = {"ms_to_1e-12": round(ms, 2), "factor_ms": round(float(np.median(tf)), 2),
                     "refine": method, "refine_iters": iters, "eta_inf": eta,
+                    "pivots_perturbed": an.pivots_perturbed(),
                     "gflops_fp64_equiv": round(flops / (ms * 1e-3) / 1e9, 1),
                     "factor_gflops": round(flops / (float(np.median(tf)) * 1e-3) / 1e9, 1)}
         out["factor_flops"] = flops
         del an
         torch.cuda.empty_cache()
-    best = min(("f32_ir", "f32_pcg"), key=lambda k: out[k]["ms_to_1e-12"])
+    best = min(("f32_ir", "f32_pcg", "bf16_pcg", "f16_pcg"), key=lambda k: out[k]["ms_to_1e-12"])
     out["mixed_best"] = best
     out["speedup_mixed_vs_fp64"] = round(out["f64"]["ms_to_1e-12"] / out[best]["ms_to_1e-12"], 3)
     return out

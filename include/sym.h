@@ -50,20 +50,43 @@ extern "C" {
 #define SYM_ORDER_NATURAL 1 /* identity */
 #define SYM_ORDER_USER 2    /* opts.perm, used exactly as given */
 
-/* factor storage precision */
+/* factor precision.
+ *   SYM_F64: FP64 panels and arithmetic.
+ *   SYM_F32: FP32 panels and arithmetic; the factorization of every diagonal
+ *     block runs in FP64 (its result rounded once to FP32).
+ *   SYM_BF16, SYM_F16: FP32 panels, the matrix scaled per device supernode
+ *     (D P A P^T D, D a power of two constant on each device supernode, from
+ *     the supernode's largest diagonal entry), and the Schur-complement
+ *     update products -- the supernodal update of Section 3.2, external and
+ *     internal -- on the bfloat16 / IEEE-half matrix cores: operands rounded
+ *     to 16 bits, products accumulated in FP32.  Diagonal factorization in
+ *     FP64 as for SYM_F32, off-diagonal triangular solves in FP32.  A pivot
+ *     below tau times its column's diagonal entry of the scaled matrix is
+ *     replaced by that value (tau = 2^pivot_floor_exp; see sym_opts and
+ *     sym_pivots_perturbed).  The solves undo the scaling, so every call
+ *     keeps its meaning (sym_export_factor returns the factor of P A P^T).
+ * Factors below FP64 are for iterative refinement (sym_refine,
+ * sym_refine_pcg). */
 #define SYM_F64 0
 #define SYM_F32 1
+#define SYM_BF16 2
+#define SYM_F16 3
+/* default pivot-floor exponents of the 16-bit update precisions */
+#define SYM_PIVOT_FLOOR_DEFAULT_BF16 (-20)
+#define SYM_PIVOT_FLOOR_DEFAULT_F16 (-24)
 
 typedef struct sym_opts {
     int32_t ordering;        /* SYM_ORDER_* (default SYM_ORDER_ND) */
     const int32_t *perm;     /* host int32[n], perm[new] = old, for SYM_ORDER_USER */
     int32_t block_width;     /* widest column block a device task handles (default 64; 16..64, multiple of 16) */
-    int32_t precision;       /* SYM_F64 (default) or SYM_F32: storage and arithmetic of L */
+    int32_t precision;       /* SYM_F64 (default), SYM_F32, SYM_BF16 or SYM_F16 (see above) */
     int32_t nd_leaf;         /* SYM_ORDER_ND: subgraphs up to this size are not split further (default 24) */
     int32_t amalgamate;      /* 1 (default): merge small supernodes into device panels with explicit
                                 zeros; 0: device panels are the fundamental supernodes.  Reported
                                 symbolic outputs are the fundamental ones either way. */
-    int32_t reserved[7];
+    int32_t pivot_floor_exp; /* SYM_BF16 / SYM_F16: tau = 2^pivot_floor_exp (-60..0); 0 = the
+                                format's default; 1 = no floor.  Ignored otherwise. */
+    int32_t reserved[6];
 } sym_opts;
 
 typedef struct sym_plan *sym_handle;
@@ -212,6 +235,11 @@ int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double
  * *info = 0, or 1 + the original index of the first column whose pivot was
  * not positive (first in elimination order).  Errors: SYM_ESTATE, SYM_EHIP. */
 int sym_status(sym_handle h, int64_t *info);
+
+/* The number of pivots the last factorization replaced by their floor
+ * (SYM_BF16 / SYM_F16 factors; 0 otherwise).  Synchronizes the bound
+ * stream.  Errors: SYM_EINVAL, SYM_ESTATE, SYM_EHIP. */
+int sym_pivots_perturbed(sym_handle h, int64_t *count);
 
 /* Copy the factor into compressed sparse column form on the host, in the
  * pattern returned by SYM_GET_LP / SYM_GET_LI (diagonal first, rows

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsym.so")
 
 SYM_ORDER_ND, SYM_ORDER_NATURAL, SYM_ORDER_USER = 0, 1, 2
-SYM_F64, SYM_F32 = 0, 1
+SYM_F64, SYM_F32, SYM_BF16, SYM_F16 = 0, 1, 2, 3
+PRECISIONS = {"f64": SYM_F64, "f32": SYM_F32, "bf16": SYM_BF16, "f16": SYM_F16}
 
 _ERRORS = {
     -1: "SYM_EINVAL", -2: "SYM_EPATTERN", -3: "SYM_ENOMEM", -4: "SYM_EHIP",
@@ -48,13 +49,14 @@ class sym_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("nd_leaf", ctypes.c_int32),
                 ("amalgamate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("pivot_floor_exp", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
            "sym_solve", "sym_solve_static", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
            "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
-           "sym_export_factor", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
+           "sym_export_factor", "sym_pivots_perturbed", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
            "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
            "sym_rhs_destroy", "sym_batch_create", "sym_batch_workspace", "sym_batch_bind",
            "sym_batch_factor", "sym_batch_solve", "sym_batch_refine", "sym_batch_eta",
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH):
     L.sym_solve_lower_sparse.argtypes = [vp, vp, vp, vp, vp]
     L.sym_status.argtypes = [vp, ctypes.POINTER(i64)]
     L.sym_export_factor.argtypes = [vp, vp, vp]
+    L.sym_pivots_perturbed.argtypes = [vp, ctypes.POINTER(i64)]
     L.sym_get_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
     L.sym_get.argtypes = [vp, ctypes.c_int, vp]
     L.sym_rhs_get.argtypes = [vp, ctypes.POINTER(i64), vp]
@@ -175,7 +178,7 @@ class Analysis:
     """
 
     def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=24,
-                 amalgamate=True):
+                 amalgamate=True, pivot_floor_exp=0):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -195,7 +198,8 @@ class Analysis:
             o.ordering = SYM_ORDER_USER
             o.perm = p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         o.block_width = int(block_width)
-        o.precision = {"f64": SYM_F64, "f32": SYM_F32}[precision]
+        o.precision = PRECISIONS[precision]
+        o.pivot_floor_exp = int(pivot_floor_exp)
         o.nd_leaf = int(nd_leaf)
         o.amalgamate = int(bool(amalgamate))
         self.precision = precision
@@ -282,6 +286,12 @@ class Analysis:
         info = ctypes.c_int64()
         _check("sym_status", self._lib.sym_status(self._h, ctypes.byref(info)))
         return info.value
+
+    def pivots_perturbed(self) -> int:
+        """Pivots the last factorization replaced by their floor."""
+        c = ctypes.c_int64()
+        _check("sym_pivots_perturbed", self._lib.sym_pivots_perturbed(self._h, ctypes.byref(c)))
+        return c.value
 
     def solve(self, b):
         """x = A^-1 b (b is not modified; returns a new tensor)."""

@@ -25,7 +25,8 @@ struct sym_plan {
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
            off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
            off_parts = 0, off_pcount = 0, off_pbuf = 0, off_invb = 0,
-           off_info = 0;
+           off_info = 0, off_dscale = 0, off_pfloor = 0, off_adiag = 0, off_acoord = 0,
+           off_dsptr = 0;
     sym::DevicePlan D;
     bool bound = false;
     bool factored = false;
@@ -58,7 +59,10 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t elem_size(const sym::Plan &P) { return P.precision == SYM_F32 ? sizeof(float) : sizeof(double); }
+size_t elem_size(const sym::Plan &P)
+{
+    return sym::prec_fp32_panels(P.precision) ? sizeof(float) : sizeof(double);
+}
 
 void layout(sym_plan *h)
 {
@@ -104,6 +108,12 @@ void layout(sym_plan *h)
     h->off_pcount = take(sizeof(int32_t) * (size_t)P.nsplit);
     h->off_pbuf = take((size_t)P.npartial * 4096 * elem_size(P));
     h->off_invb = take(sizeof(int32_t) * P.inv_blocks.size());
+    const bool sc = sym::prec_scaled(P.precision);
+    h->off_dscale = take(sc ? sizeof(double) * (size_t)P.n : 0);
+    h->off_pfloor = take(sc ? sizeof(double) * (size_t)P.n : 0);
+    h->off_adiag = take(sc ? sizeof(int64_t) * P.adiag.size() : 0);
+    h->off_acoord = take(sc ? sizeof(int32_t) * P.acoord.size() : 0);
+    h->off_dsptr = take(sc ? sizeof(int32_t) * P.dsptr.size() : 0);
     h->ws_bytes = o;
 }
 
@@ -146,6 +156,7 @@ void sym_opts_default(sym_opts *o)
     o->precision = SYM_F64;
     o->nd_leaf = 24;
     o->amalgamate = 1;
+    o->pivot_floor_exp = 0;
 }
 
 int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts *opts,
@@ -156,12 +167,21 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
     sym_opts o;
     sym_opts_default(&o);
     if (opts) o = *opts;
-    if (o.precision != SYM_F64 && o.precision != SYM_F32) return SYM_EINVAL;
+    if (o.precision < SYM_F64 || o.precision > SYM_F16) return SYM_EINVAL;
+    if (o.pivot_floor_exp < -60 || o.pivot_floor_exp > 1) return SYM_EINVAL;
     sym_plan *h = new (std::nothrow) sym_plan();
     if (!h) return SYM_ENOMEM;
     int rc;
     try {
         h->P.precision = o.precision;
+        // pivot floor of the scaled precisions: 2^exp, the default by format
+        // (SYM_PIVOT_FLOOR_DEFAULT_*), or none (exp = 1)
+        if (sym::prec_scaled(o.precision) && o.pivot_floor_exp != 1) {
+            const int e = o.pivot_floor_exp != 0 ? o.pivot_floor_exp
+                          : o.precision == SYM_BF16 ? SYM_PIVOT_FLOOR_DEFAULT_BF16
+                                                    : SYM_PIVOT_FLOOR_DEFAULT_F16;
+            h->P.pivot_floor = std::ldexp(1.0, e);
+        }
         rc = sym::analyze(n, Ap, Ai, o.ordering, o.perm, o.block_width ? o.block_width : 64,
                           o.nd_leaf > 0 ? o.nd_leaf : 24, o.amalgamate != 0, h->P);
         if (rc == SYM_OK) layout(h);
@@ -232,7 +252,18 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.pcount = (int32_t *)(base + h->off_pcount);
     D.pbuf = base + h->off_pbuf;
     D.inv_blocks = (int32_t *)(base + h->off_invb);
+    const bool sc = sym::prec_scaled(P.precision);
+    D.dscale = sc ? (double *)(base + h->off_dscale) : nullptr;
+    D.pfloor = sc ? (double *)(base + h->off_pfloor) : nullptr;
+    D.adiag = sc ? (int64_t *)(base + h->off_adiag) : nullptr;
+    D.acoord = sc ? (int32_t *)(base + h->off_acoord) : nullptr;
+    D.dsptr = sc ? (int32_t *)(base + h->off_dsptr) : nullptr;
     hipError_t e = hipSuccess;
+    if (sc) {
+        e = upload(D.adiag, P.adiag.data(), sizeof(int64_t) * P.adiag.size(), s);
+        if (e == hipSuccess) e = upload(D.acoord, P.acoord.data(), sizeof(int32_t) * P.acoord.size(), s);
+        if (e == hipSuccess) e = upload(D.dsptr, P.dsptr.data(), sizeof(int32_t) * P.dsptr.size(), s);
+    }
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
     if (e == hipSuccess) e = upload(D.tasks, P.ftasks.data(), sizeof(sym::Task) * P.ftasks.size(), s);
@@ -307,6 +338,8 @@ int sym_solve_upper(sym_handle h, double *y_dev, void *stream)
     hipStream_t s = (hipStream_t)stream;
     h->stream = s;
     if (sym::launch_bwd(h->P, h->D, y_dev, s) != hipSuccess) return SYM_EHIP;
+    // L = D^{-1} L-hat for a scaled factor, so L^{-T} y = D L-hat^{-T} y
+    if (sym::launch_scale(h->P, h->D, y_dev, s) != hipSuccess) return SYM_EHIP;
     return SYM_OK;
 }
 
@@ -604,6 +637,17 @@ int sym_status(sym_handle h, int64_t *info)
     return SYM_OK;
 }
 
+int sym_pivots_perturbed(sym_handle h, int64_t *count)
+{
+    if (!h || !count) return SYM_EINVAL;
+    if (!h->bound || !h->factored) return SYM_ESTATE;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return SYM_EHIP;
+    int32_t w[4];
+    if (hipMemcpy(w, h->D.info, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return SYM_EHIP;
+    *count = w[3];
+    return SYM_OK;
+}
+
 int sym_export_factor(sym_handle h, double *Lx_host, void *stream)
 {
     if (!h || (!Lx_host && h->P.nnzL)) return SYM_EINVAL;
@@ -621,6 +665,18 @@ int sym_export_factor(sym_handle h, double *Lx_host, void *stream)
     if (!panel.empty() &&
         hipMemcpy(panel.data(), h->D.Lx, panel.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return SYM_EHIP;
+    // a scaled factor holds D L: row i divided by d_i gives L
+    std::vector<double> dsc;
+    if (h->D.dscale) {
+        try {
+            dsc.resize((size_t)P.n);
+        } catch (const std::bad_alloc &) {
+            return SYM_ENOMEM;
+        }
+        if (P.n > 0 && hipMemcpy(dsc.data(), h->D.dscale, sizeof(double) * (size_t)P.n,
+                                 hipMemcpyDeviceToHost) != hipSuccess)
+            return SYM_EHIP;
+    }
     int64_t q = 0;
     for (int32_t s = 0; s < P.ns; ++s) {
         const int32_t *frows = P.srows.data() + P.srowptr[s];
@@ -632,8 +688,10 @@ int sym_export_factor(sym_handle h, double *Lx_host, void *stream)
             for (int32_t p = c - P.sptr[s]; p < fr; ++p) {
                 const int32_t lr = (int32_t)(std::lower_bound(drows + lc, drows + d.r, frows[p]) - drows);
                 const int64_t off = d.valoff + (int64_t)lc * d.ld + lr;
-                Lx_host[q++] = P.precision == SYM_F32 ? (double)((const float *)panel.data())[off]
-                                                      : ((const double *)panel.data())[off];
+                double v = es == sizeof(float) ? (double)((const float *)panel.data())[off]
+                                               : ((const double *)panel.data())[off];
+                if (!dsc.empty()) v /= dsc[frows[p]];
+                Lx_host[q++] = v;
             }
         }
     }
@@ -831,7 +889,7 @@ struct sym_batch {
     sym_plan *h = nullptr;
     int32_t m = 0;
     size_t ws_bytes = 0, off_Lx = 0, off_vec = 0, off_vec2 = 0, off_vec3 = 0, off_info = 0,
-           off_red = 0, off_sync = 0, off_pcount = 0, off_pbuf = 0;
+           off_red = 0, off_sync = 0, off_pcount = 0, off_pbuf = 0, off_dscale = 0, off_pfloor = 0;
     sym::DevicePlan D;              // the analysis's plan arrays, the batch's own buffers
     bool bound = false, factored = false;
     uint64_t generation = 0;        // the analysis's generation when the batch was bound
@@ -867,6 +925,9 @@ int sym_batch_create(sym_handle h, int32_t m, sym_batch_t *out)
     b->off_sync = take(M * sizeof(int32_t) * (2 * (size_t)P.nb + 16));
     b->off_pcount = take(M * sizeof(int32_t) * (size_t)P.nsplit);
     b->off_pbuf = take(M * (size_t)P.npartial * 4096 * elem_size(P));
+    const bool sc = sym::prec_scaled(P.precision);
+    b->off_dscale = take(sc ? M * sizeof(double) * (size_t)P.n : 0);
+    b->off_pfloor = take(sc ? M * sizeof(double) * (size_t)P.n : 0);
     b->ws_bytes = std::max<size_t>(o, 256);
     *out = b;
     return SYM_OK;
@@ -899,6 +960,10 @@ int sym_batch_bind(sym_batch_t b, void *dev_ws, size_t bytes, void *stream)
     D.ticket = D.done + (size_t)b->m * P.nb;
     D.pcount = (int32_t *)(base + b->off_pcount);
     D.pbuf = base + b->off_pbuf;
+    if (sym::prec_scaled(P.precision)) {
+        D.dscale = (double *)(base + b->off_dscale);
+        D.pfloor = (double *)(base + b->off_pfloor);
+    }
     // single-instance scratch of the analysis is not used by batches
     D.vec4 = D.vec5 = D.vec6 = D.part = nullptr;
     D.ttime = nullptr;

@@ -59,6 +59,13 @@ struct DevicePlan {
     int32_t *pend = nullptr;        // nb: live counters
     int32_t *done = nullptr;        // nb: blocks whose backward solve is final
     int32_t *ticket = nullptr;      // next task of a running sweep
+    // per-supernode scaling (scaled precisions; null otherwise): the factor
+    // is that of D P A P^T D, D = diag(dscale) in permuted numbering
+    double *dscale = nullptr;       // n (per instance)
+    double *pfloor = nullptr;       // n (per instance): pivot floors
+    int64_t *adiag = nullptr;       // n
+    int32_t *acoord = nullptr;      // 2 nnzA
+    int32_t *dsptr = nullptr;       // nds + 1
 };
 
 // Reach-pruned forward sweep schedule, device view.
@@ -106,6 +113,9 @@ hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t
 hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs &R,
                              int64_t nbeta, const double *bv, double *acc, double *out,
                              hipStream_t s);
+// y *= dscale (permuted numbering, per instance): the scaling's half of a
+// backward sweep's result
+hipError_t launch_scale(const Plan &P, const DevicePlan &D, double *y, hipStream_t s);
 
 // ---- iterative refinement (refine.hip)
 // r = b - A x (FP64); red[0] = max |r_i|, red[1] = max_i sum_j |A_ij|,

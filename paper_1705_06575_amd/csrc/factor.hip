@@ -99,15 +99,35 @@ __device__ __forceinline__ void tile2_in(T *d1, const T *__restrict__ s1, int n1
     }
 }
 
-// The reverse of tile_in: LDS block to global memory.
-template <typename T>
-__device__ __forceinline__ void tile_out(T *__restrict__ dst, const T *src, int64_t ld, int nr, int w)
+// The reverse of tile_in: LDS block to global memory (an FP64 block into
+// FP32 panels is rounded once, here).
+template <typename T, typename U>
+__device__ __forceinline__ void tile_out(T *__restrict__ dst, const U *src, int64_t ld, int nr, int w)
 {
     const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int c = c0 + 4 * u;
-        if (i < nr && c < w) dst[(int64_t)c * ld + i] = src[c * LDC + i];
+        if (i < nr && c < w) dst[(int64_t)c * ld + i] = (T)src[c * LDC + i];
+    }
+}
+
+// An FP32 tile (the first half of an FP64-sized LDS buffer) widened in place
+// to FP64, for the diagonal factorization; called by all threads.  Every
+// entry is read before any is written.
+template <typename T>
+__device__ __forceinline__ void widen_tile(double *buf)
+{
+    if constexpr (sizeof(T) == sizeof(float)) {
+        const float *f = reinterpret_cast<const float *>(buf);
+        const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = f[(c0 + 4 * u) * LDC + i];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) buf[(c0 + 4 * u) * LDC + i] = (double)v[u];
+        __syncthreads();
     }
 }
 
@@ -123,15 +143,56 @@ __global__ void k_fill_zero(T *__restrict__ x, int64_t count)
         x[i] = T(0);
 }
 
+// Ax into the panels; with scaling (dscale != null) the entry (i, j) of
+// P A P^T goes in as d_i a_ij d_j (acoord: its permuted row and column).
 template <typename T>
 __global__ void k_scatter_a(const double *__restrict__ Ax, const int64_t *__restrict__ amap,
-                            T *__restrict__ Lx, int64_t nnz, int64_t lx_stride)
+                            T *__restrict__ Lx, int64_t nnz, int64_t lx_stride,
+                            const double *__restrict__ dscale, const int32_t *__restrict__ acoord,
+                            int32_t n)
 {
     Ax += blockIdx.y * nnz;
     Lx += blockIdx.y * lx_stride;
+    if (dscale) dscale += (int64_t)blockIdx.y * n;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
-         k += (int64_t)gridDim.x * blockDim.x)
-        Lx[amap[k]] = (T)Ax[k];
+         k += (int64_t)gridDim.x * blockDim.x) {
+        double v = Ax[k];
+        if (dscale) v *= dscale[acoord[2 * k]] * dscale[acoord[2 * k + 1]];
+        Lx[amap[k]] = (T)v;
+    }
+}
+
+// Per-supernode scaling of the factored matrix: D = diag(d) with d_j =
+// 2^-e_s for every column j of device supernode s, e_s = floor(E / 2) where
+// 2^(E-1) <= max_{j in s} c_jj < 2^E (c_jj: the diagonal of P A P^T), so the
+// largest diagonal entry of the supernode's columns in D P A P^T D lies in
+// [1/2, 2).  Powers of two scale exactly.  The pivot floor of column j, if
+// asked for, is tau times its diagonal entry in the scaled matrix.  One
+// thread per device supernode; adiag[j]: index of c_jj in Ax (-1 if absent).
+__global__ void k_super_scale(const double *__restrict__ Ax, const int64_t *__restrict__ adiag,
+                              const int32_t *__restrict__ dsptr, int32_t nds, int64_t nnz,
+                              int32_t n, double *__restrict__ dscale, double *__restrict__ pfloor,
+                              double tau)
+{
+    Ax += blockIdx.y * nnz;
+    dscale += (int64_t)blockIdx.y * n;
+    if (pfloor) pfloor += (int64_t)blockIdx.y * n;
+    for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < nds; s += gridDim.x * blockDim.x) {
+        double m = 0.0;
+        for (int32_t j = dsptr[s]; j < dsptr[s + 1]; ++j)
+            if (adiag[j] >= 0) m = fmax(m, Ax[adiag[j]]);
+        double d = 1.0;
+        if (m > 0.0 && m < __builtin_huge_val()) {
+            int E = 0;
+            (void)frexp(m, &E);
+            const int e = E >= 0 ? E / 2 : -((1 - E) / 2);   // floor(E / 2)
+            d = ldexp(1.0, -e);
+        }
+        for (int32_t j = dsptr[s]; j < dsptr[s + 1]; ++j) {
+            dscale[j] = d;
+            if (pfloor) pfloor[j] = adiag[j] >= 0 ? tau * (d * d) * Ax[adiag[j]] : 0.0;
+        }
+    }
 }
 
 __global__ void k_info_reset(int32_t *info)
@@ -140,6 +201,7 @@ __global__ void k_info_reset(int32_t *info)
     info[0] = INT32_MAX;
     info[1] = INT32_MAX;
     info[2] = 0;
+    info[3] = 0;
 }
 
 // First position p in [lo, hi) with a[p] >= key (a sorted ascending); every
@@ -167,6 +229,68 @@ __device__ __forceinline__ int wave_lower_bound(const int32_t *__restrict__ a, i
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+// Operand format of the update products (external and internal updates):
+// the panels' own type, or FP32 panel values rounded (to nearest even) to
+// bfloat16 or IEEE half on their way to the 16-bit matrix cores, which
+// accumulate in FP32.  The tiles, the diagonal factorization and the
+// off-diagonal solves never leave the panels' precision (or FP64).
+constexpr int kOpNative = 0, kOpBF16 = 1, kOpF16 = 2;
+
+// acc += A B over four k-steps in one 16 x 16 x 16 matrix-core product:
+// lane l supplies a[s] = A[l % 16][k_s(l)] and b[s] = B[k_s(l)][l % 16] for
+// s < 4.  Any map of (s, l / 16) to 16 distinct inner indices is valid as
+// long as both operands use the same one, so the four k-steps of the
+// 16 x 16 x 4 form (k = 4 s + l / 16) go into one instruction unchanged.
+template <int OP>
+__device__ __forceinline__ f4 mma_pack(const float (&a)[4], const float (&b)[4], f4 c)
+{
+    if constexpr (OP == kOpBF16) {
+        s4v x, y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            x[i] = __builtin_bit_cast(short, (__bf16)a[i]);
+            y[i] = __builtin_bit_cast(short, (__bf16)b[i]);
+        }
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, c, 0, 0, 0);
+    } else {
+        h4v x, y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            x[i] = (_Float16)a[i];
+            y[i] = (_Float16)b[i];
+        }
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(x, y, c, 0, 0, 0);
+    }
+}
+
+// Four values of one row (or column) packed for mma_pack's operand, and the
+// packed product of two such operands.
+template <int OP>
+__device__ __forceinline__ uint64_t pack4(const float (&v)[4])
+{
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint16_t h;
+        if constexpr (OP == kOpBF16) h = __builtin_bit_cast(uint16_t, (__bf16)v[i]);
+        else h = __builtin_bit_cast(uint16_t, (_Float16)v[i]);
+        r |= (uint64_t)h << (16 * i);
+    }
+    return r;
+}
+template <int OP>
+__device__ __forceinline__ f4 mma_packed(uint64_t a, uint64_t b, f4 c)
+{
+    if constexpr (OP == kOpBF16)
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a),
+                                                         __builtin_bit_cast(s4v, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4v, a),
+                                                     __builtin_bit_cast(h4v, b), c, 0, 0, 0);
+}
 
 // 16x16x4 matrix-core product per wavefront.  Operands: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element v of lane l
@@ -201,7 +325,7 @@ template <typename T>
 struct Chunk16 {
     T a0[4], a1[4], b0[4], b1[4];
 };
-template <typename T>
+template <typename T, int OP>
 __device__ __forceinline__ void wave_product_pipe(const T *__restrict__ pa, const T *__restrict__ pb,
                                                   int64_t ld, int nI, int nJ, int wk, int wr, int wc,
                                                   typename Mfma<T>::acc_t (&acc)[2][2])
@@ -226,14 +350,31 @@ __device__ __forceinline__ void wave_product_pipe(const T *__restrict__ pa, cons
         }
     };
     auto compute = [&](const Chunk16<T> &x, int kc) {
+        if constexpr (OP == kOpNative) {
 #pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            const bool vk = kc + 4 * st + lk < wk;
-            const T x0 = vk ? -x.a0[st] : T(0), x1 = vk ? -x.a1[st] : T(0);
-            acc[0][0] = Mfma<T>::mma(x0, x.b0[st], acc[0][0]);
-            acc[0][1] = Mfma<T>::mma(x0, x.b1[st], acc[0][1]);
-            acc[1][0] = Mfma<T>::mma(x1, x.b0[st], acc[1][0]);
-            acc[1][1] = Mfma<T>::mma(x1, x.b1[st], acc[1][1]);
+            for (int st = 0; st < 4; ++st) {
+                const bool vk = kc + 4 * st + lk < wk;
+                const T x0 = vk ? -x.a0[st] : T(0), x1 = vk ? -x.a1[st] : T(0);
+                acc[0][0] = Mfma<T>::mma(x0, x.b0[st], acc[0][0]);
+                acc[0][1] = Mfma<T>::mma(x0, x.b1[st], acc[0][1]);
+                acc[1][0] = Mfma<T>::mma(x1, x.b0[st], acc[1][0]);
+                acc[1][1] = Mfma<T>::mma(x1, x.b1[st], acc[1][1]);
+            }
+        } else {
+            // the chunk's four k-steps in one 16-bit product per quadrant
+            float x0[4], x1[4], y0[4], y1[4];
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const bool vk = kc + 4 * st + lk < wk;
+                x0[st] = vk ? -x.a0[st] : 0.0f;
+                x1[st] = vk ? -x.a1[st] : 0.0f;
+                y0[st] = x.b0[st];
+                y1[st] = x.b1[st];
+            }
+            acc[0][0] = mma_pack<OP>(x0, y0, acc[0][0]);
+            acc[0][1] = mma_pack<OP>(x0, y1, acc[0][1]);
+            acc[1][0] = mma_pack<OP>(x1, y0, acc[1][0]);
+            acc[1][1] = mma_pack<OP>(x1, y1, acc[1][1]);
         }
     };
     // an even number of chunks (at least two); the last pair has no loads
@@ -298,24 +439,34 @@ __device__ __forceinline__ float pivot_rsqrt(float d)
 // entries above the diagonal receive harmless updates (they are stored and
 // never read).  Columns past wb start at zero, never feed the real ones
 // (only later columns depend on a column) and are not stored.
+// With a pivot floor (floor != null: floor[c] for the block's column c), a
+// pivot below its column's floor is replaced by the floor (the factor is
+// then that of a matrix with a slightly larger diagonal; the count of
+// replacements goes to info[3]); a NaN pivot is never replaced.
 template <typename T>
 __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
-                                              int32_t *info)
+                                              int32_t *info, const double *floor)
 {
     __shared__ double bcast[64];
     const int lane = threadIdx.x & 63;
     const int row = c0 + lane;
     const bool mine = row < nr;
-    // the diagonal factorization runs in FP64 whatever the storage type
-    // (for FP32 factors: FP64 pivots, reciprocal square roots and in-panel
-    // updates on the FP32 values, rounded once when stored)
     double r[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? (double)C[(c0 + c) * LDC + row] : 0.0;
-    int bad = INT_MAX;
+    const double fl = floor ? floor[c0 + min(lane & 15, wb - 1)] : 0.0;
+    int bad = INT_MAX, nrep = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const double d = lane_value(r[k], k);
+        double d = lane_value(r[k], k);
+        if (floor) {
+            const double f = lane_value(fl, k);
+            if (k < wb && d < f) {
+                if (lane == k) r[k] = f;
+                d = f;
+                ++nrep;
+            }
+        }
         bad = (k < wb && !(d > 0.0)) ? min(bad, col0 + c0 + k) : bad;
         r[k] *= pivot_rsqrt(d);
         if (k + 1 < 16) r[k + 1] = fma(-r[k], lane_value(r[k], k + 1), r[k + 1]);
@@ -329,6 +480,7 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
         }
     }
     if (bad != INT_MAX && lane == 0) atomicMin(info, bad);
+    if (nrep && lane == 0) atomicAdd(info + 3, nrep);
 #pragma unroll
     for (int c = 0; c < 16; ++c)
         if (mine && c < wb) C[(c0 + c) * LDC + row] = (T)r[c];
@@ -455,18 +607,21 @@ __device__ __forceinline__ void block_update(T *C, const T *X, const T *Y, int r
 // j + 1 while wavefronts 1..3 apply sub-panel j's update to the columns
 // beyond it (matrix-core products).  Every column still receives the
 // sub-panels' updates in order.  Called by all threads of the workgroup.
+// Every factorization of a diagonal block runs here in FP64 (FP32 panels
+// are widened into an FP64 tile first and rounded once when stored).
 template <typename T>
-__device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info)
+__device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info,
+                                             const double *floor)
 {
     const int wave = threadIdx.x >> 6;
-    if (wave == 0) wave_subpanel(C, 0, min(16, w), nr, col0, info);
+    if (wave == 0) wave_subpanel(C, 0, min(16, w), nr, col0, info, floor);
     __syncthreads();
     for (int c0 = 16; c0 < w; c0 += 16) {
         const int wb = min(16, w - c0);
         block_update(C, C, C, c0, nr, c0, c0 + wb, c0 - 16, 16, 0);
         __syncthreads();
         if (wave == 0)
-            wave_subpanel(C, c0, wb, nr, col0, info);
+            wave_subpanel(C, c0, wb, nr, col0, info, floor);
         else if (c0 + wb < w)
             block_update(C, C, C, c0 + wb, nr, c0 + wb, w, c0 - 16, 16, 0, 1);
         __syncthreads();
@@ -592,6 +747,89 @@ __device__ __forceinline__ void coop_product(T *C, T (*As)[KC][64], T (*Bs)[KC][
     __syncthreads();
 }
 
+// The same product with the operands on the 16-bit matrix cores (FP32
+// panels): chunks of 16 inner indices; thread (r, kq) loads row r's values
+// at k = kc + kq + 4 j (j < 4) -- exactly the four k-steps that lane
+// 16 kq + r % 16 of a wavefront supplies to one 16 x 16 x 16 product -- and
+// stores them packed (8 bytes) at stage[kq][r], so a wavefront's operand is
+// one LDS read.  Rows and columns past the product's extent and inner
+// indices past wk are zero in the stage.
+template <int OP>
+__device__ __forceinline__ void stage_packed(uint64_t (*As)[64], uint64_t (*Bs)[64],
+                                             const float (&va)[4], const float (&vb)[4])
+{
+    const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;
+    As[kq][r] = pack4<OP>(va);
+    Bs[kq][r] = pack4<OP>(vb);
+}
+
+template <int OP>
+__device__ __forceinline__ void coop_product_packed(float *C, uint64_t (*As)[4][64],
+                                                    uint64_t (*Bs)[4][64], int32_t *s_rel,
+                                                    const Incidence &in,
+                                                    const uint8_t *__restrict__ imap,
+                                                    const float *__restrict__ Lx, int r0, int nr,
+                                                    int w)
+{
+    constexpr int KC = 16;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const float *LK = Lx + in.valoff;
+    const int nI = in.nI, nJ = in.nJ;
+    const uint8_t *mp = imap + in.mapoff;
+    if (tid < 64) s_rel[tid] = tid < nI ? (int)mp[tid] : 0;
+    else if (tid < 128) s_rel[tid] = tid - 64 < nJ ? (int)mp[nI + tid - 64] : 0;
+    const int nch = (in.wk + KC - 1) / KC;
+    float pa[2][4], pb[2][4];
+    load_chunk<float, KC>(pa[0], pb[0], LK, in, 0);
+    if (nch > 1) load_chunk<float, KC>(pa[1], pb[1], LK, in, KC);
+    stage_packed<OP>(As[0], Bs[0], pa[0], pb[0]);
+    if (nch > 2) load_chunk<float, KC>(pa[0], pb[0], LK, in, 2 * KC);
+    __syncthreads();
+    const bool active = 32 * wr < nI && 32 * wc < nJ;
+    const bool a1v = 32 * wr + 16 < nI, b1v = 32 * wc + 16 < nJ;
+    f4 acc[2][2] = {};
+    const int li = lane & 15, g = lane >> 4;
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (active) {
+            const uint64_t a0 = As[buf][g][32 * wr + li];
+            const uint64_t a1 = As[buf][g][32 * wr + 16 + li];
+            const uint64_t b0 = Bs[buf][g][32 * wc + li];
+            const uint64_t b1 = Bs[buf][g][32 * wc + 16 + li];
+            acc[0][0] = mma_packed<OP>(a0, b0, acc[0][0]);
+            if (b1v) acc[0][1] = mma_packed<OP>(a0, b1, acc[0][1]);
+            if (a1v) acc[1][0] = mma_packed<OP>(a1, b0, acc[1][0]);
+            if (a1v && b1v) acc[1][1] = mma_packed<OP>(a1, b1, acc[1][1]);
+        }
+        if (c + 1 < nch) {
+            const int rs = (c + 1) & 1;
+            stage_packed<OP>(As[buf ^ 1], Bs[buf ^ 1], pa[rs], pb[rs]);
+            if (c + 3 < nch) load_chunk<float, KC>(pa[rs], pb[rs], LK, in, KC * (c + 3));
+        }
+        __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n2 = 0; n2 < 2; ++n2) {
+                const int col = 32 * wc + 16 * n2 + li;
+                const int Cc = s_rel[64 + (col < 64 ? col : 0)];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 32 * wr + 16 * m + Mfma<float>::row(lane, v);
+                    if (row < nI && col < nJ) {
+                        const int R = s_rel[row];
+                        if (R < nr && Cc < w && r0 + R >= Cc) C[Cc * LDC + R] -= acc[m][n2][v];
+                    }
+                }
+            }
+    }
+    __syncthreads();
+}
+
 // ---- wavefront items (small incidences)
 //
 // A wavefront runs its item list as one stream of operand batches.  A batch
@@ -669,19 +907,35 @@ __device__ __forceinline__ void issue(Batch<T> &r, const T *__restrict__ Lx,
     }
 }
 
-template <typename T>
+template <typename T, int OP>
 __device__ __forceinline__ void compute(const Batch<T> &r, typename Mfma<T>::acc_t (&acc)[4],
                                         const Item &it, int kb, int lane)
 {
     const int nrb = item_nrb(it);
+    if constexpr (OP == kOpNative) {
 #pragma unroll
-    for (int s = 0; s < kSteps; ++s) {
-        if (4 * (kb + s) < it.wk) {
-            const bool vk = 4 * (kb + s) + (lane >> 4) < it.wk;
-            const T b = vk ? r.b[s] : T(0);
+        for (int s = 0; s < kSteps; ++s) {
+            if (4 * (kb + s) < it.wk) {
+                const bool vk = 4 * (kb + s) + (lane >> 4) < it.wk;
+                const T b = vk ? r.b[s] : T(0);
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m < nrb) acc[m] = Mfma<T>::mma(r.a[s][m], b, acc[m]);
+                for (int m = 0; m < 4; ++m)
+                    if (m < nrb) acc[m] = Mfma<T>::mma(r.a[s][m], b, acc[m]);
+            }
+        }
+    } else {
+        // the batch's four k-steps in one 16-bit product per row block
+        // (a batch exists only while 4 kb < wk)
+        static_assert(kSteps == 4, "one 16-bit product covers four k-steps");
+        float b[4];
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) b[s] = 4 * (kb + s) + (lane >> 4) < it.wk ? r.b[s] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m < nrb) {
+                const float a[4] = {r.a[0][m], r.a[1][m], r.a[2][m], r.a[3][m]};
+                acc[m] = mma_pack<OP>(a, b, acc[m]);
+            }
         }
     }
 }
@@ -710,7 +964,7 @@ __device__ __forceinline__ void scatter(T *C, typename Mfma<T>::acc_t (&acc)[4],
     }
 }
 
-template <typename T>
+template <typename T, int OP>
 __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ items,
                                            const uint8_t *__restrict__ wmap,
                                            const T *__restrict__ Lx, int64_t i0, int64_t i1, int r0,
@@ -737,7 +991,7 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
             ++inx;
             nxt = load_item(items, min(inx, i1 - 1));
         }
-        compute(P, acc, cur, kb, lane);
+        compute<T, OP>(P, acc, cur, kb, lane);
         if (!same) scatter(C, acc, P, cur, r0, nr, w, lane);
         cur = ni;
         kb = nkb;
@@ -747,7 +1001,7 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
     }
 }
 
-template <typename T, bool COOP>
+template <typename T, bool COOP, int OP>
 __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tasks,
                                                  const int64_t *__restrict__ iptr,
                                                  const int64_t *__restrict__ ibig,
@@ -762,17 +1016,19 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
                                                  unsigned long long *__restrict__ ttime,
                                                  const PartDesc *__restrict__ parts,
                                                  int32_t *pcount, T *pbuf, int32_t nsplit,
-                                                 int64_t npartial)
+                                                 int64_t npartial, const double *__restrict__ pfloor,
+                                                 int32_t n)
 {
     const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
-    __shared__ T C[64 * LDC];
-    constexpr int KC = 8;   // inner indices per staged chunk of the cooperative product
-    __shared__ T As[COOP ? 2 : 1][KC][64];
+    // the tile, in the panels' precision; FP64-sized so that a fused
+    // diagonal factorization can widen it in place
+    __shared__ double Cbuf[64 * LDC];
+    T *C = reinterpret_cast<T *>(Cbuf);
     Lx += blockIdx.y * lx_stride;
     info += 4 * blockIdx.y;
     pcount += (int64_t)blockIdx.y * nsplit;
     pbuf += (int64_t)blockIdx.y * npartial * 4096;
-    __shared__ T Bs[COOP ? 2 : 1][KC][64];
+    if (pfloor) pfloor += (int64_t)blockIdx.y * n;
     __shared__ int32_t s_rel[COOP ? 128 : 1];
     __shared__ int s_last;
 
@@ -796,7 +1052,10 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     __syncthreads();
 
     int64_t q = iptr[blockIdx.x];
-    if constexpr (COOP) {
+    if constexpr (COOP && OP == kOpNative) {
+        constexpr int KC = 8;   // inner indices per staged chunk of the cooperative product
+        __shared__ T As[2][KC][64];
+        __shared__ T Bs[2][KC][64];
         const int64_t qb = ibig[blockIdx.x];
         for (; q < qb; ++q) {
             const Incidence in = incs[q];
@@ -806,12 +1065,24 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
             }
             coop_product<T, KC>(C, As, Bs, s_rel, in, imap, Lx, r0, nr, w);
         }
+    } else if constexpr (COOP) {
+        __shared__ uint64_t Ap[2][4][64];
+        __shared__ uint64_t Bp[2][4][64];
+        const int64_t qb = ibig[blockIdx.x];
+        for (; q < qb; ++q) {
+            const Incidence in = incs[q];
+            if (in.nI > nr || in.nJ > w) {
+                if (tid == 0) atomicMin(info + 1, tk.J);
+                continue;
+            }
+            coop_product_packed<OP>(C, Ap, Bp, s_rel, in, imap, Lx, r0, nr, w);
+        }
     }
 
     // the small incidences: each wavefront runs its own item list
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int64_t i0 = wptr[4 * blockIdx.x + wv], i1 = wptr[4 * blockIdx.x + wv + 1];
-    if (i0 < i1) wave_items(C, witems, wmap, (const T *)Lx, i0, i1, r0, nr, w);
+    if (i0 < i1) wave_items<T, OP>(C, witems, wmap, (const T *)Lx, i0, i1, r0, nr, w);
     __syncthreads();
 
     bool finish = !partial;
@@ -865,8 +1136,13 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
         }
     }
     if (finish) {
-        if (tk.flags & kFuseFactor) panel_factor(C, nr, w, J.col0, info);
-        tile_out(LJ + r0, C, J.ld, nr, w);
+        if (tk.flags & kFuseFactor) {
+            widen_tile<T>(Cbuf);
+            panel_factor(Cbuf, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
+            tile_out(LJ + r0, Cbuf, J.ld, nr, w);
+        } else {
+            tile_out(LJ + r0, C, J.ld, nr, w);
+        }
     }
     if (ttime && blockIdx.y == 0) {
         __syncthreads();                    // every wavefront's work is issued
@@ -879,15 +1155,17 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
 // J's local row 0 is K's local row d = col0_J - col0_K, so no index lookups
 // are needed.  The accumulators start from the tile's current values.  With
 // kFuseFactor (tile 0 of block K+1) the result is factored in LDS.
-template <typename T>
+template <typename T, int OP>
 __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tasks,
                                                  const BlockDesc *__restrict__ blk,
                                                  T *__restrict__ Lx, int32_t *__restrict__ info,
-                                                 int64_t lx_stride)
+                                                 int64_t lx_stride, const double *__restrict__ pfloor,
+                                                 int32_t n)
 {
     Lx += blockIdx.y * lx_stride;
     info += 4 * blockIdx.y;
-    __shared__ T C[64 * LDC];
+    if (pfloor) pfloor += (int64_t)blockIdx.y * n;
+    __shared__ double C[64 * LDC];      // the fused tile, factored in FP64
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -922,7 +1200,7 @@ __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tas
                     const T val = *reinterpret_cast<const T *>(tb + off);
                     acc[m][n][v] = ok ? val : T(0);
                 }
-        wave_product_pipe<T>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
+        wave_product_pipe<T, OP>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
     }
     if (tk.flags & kFuseFactor) {
         if (active) {
@@ -934,11 +1212,11 @@ __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tas
                     for (int v = 0; v < 4; ++v) {
                         const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
                         const int col = 32 * wc + 16 * n + (lane & 15);
-                        if (row < nr && col < w) C[col * LDC + row] = acc[m][n][v];
+                        if (row < nr && col < w) C[col * LDC + row] = (double)acc[m][n][v];
                     }
         }
         __syncthreads();
-        panel_factor(C, nr, w, J.col0, info);
+        panel_factor(C, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
         tile_out(LJ + r0, C, J.ld, nr, w);
     } else if (active) {
 #pragma unroll
@@ -1098,13 +1376,14 @@ struct Bracket {
     }
 };
 
-template <typename T>
+template <typename T, int OP>
 hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hipStream_t s,
                        FactorProfile *prof)
 {
     T *Lx = (T *)D.Lx;
     const unsigned m = (unsigned)D.m;
     const int64_t lxs = P.panel_entries;
+    const double *pfloor = P.pivot_floor > 0.0 ? D.pfloor : nullptr;
     // per-task durations are recorded while profiling a single factorization
     auto ttime = [&](const Phase &ph) {
         return (prof && D.ttime && D.m == 1) ? (unsigned long long *)(D.ttime + ph.t0) : nullptr;
@@ -1112,27 +1391,35 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
     if (prof) prof->used = 0;
     {
         Bracket b(prof, s, 0);
+        if (D.dscale && P.nds > 0)
+            k_super_scale<<<dim3(grid_for(P.nds), m), 256, 0, s>>>(Ax, D.adiag, D.dsptr, P.nds,
+                                                                    P.nnzA, P.n, D.dscale,
+                                                                    pfloor ? D.pfloor : nullptr,
+                                                                    P.pivot_floor);
         if (P.panel_entries > 0)
             k_fill_zero<T><<<dim3(grid_for(P.panel_entries), m), 256, 0, s>>>(Lx, P.panel_entries);
         if (P.nnzA > 0)
-            k_scatter_a<T><<<dim3(grid_for(P.nnzA), m), 256, 0, s>>>(Ax, D.amap, Lx, P.nnzA, lxs);
+            k_scatter_a<T><<<dim3(grid_for(P.nnzA), m), 256, 0, s>>>(Ax, D.amap, Lx, P.nnzA, lxs,
+                                                                      D.dscale, D.acoord, P.n);
         k_info_reset<<<dim3(1, m), 1, 0, s>>>(D.info);
     }
     for (const Phase &ph : P.phases) {
         const dim3 g((unsigned)(ph.t1 - ph.t0), m);
         Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
-            k_external<T, true><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
-                                                 D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                 D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
-                                                 D.pcount, (T *)D.pbuf, P.nsplit, P.npartial);
+            k_external<T, true, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
+                                                     D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
+                                                     D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
+                                                     D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
+                                                     pfloor, P.n);
         else if (ph.kind == kPhaseExternal)
-            k_external<T, false><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
-                                                  D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
-                                                  D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
-                                                  D.pcount, (T *)D.pbuf, P.nsplit, P.npartial);
+            k_external<T, false, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
+                                                      D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
+                                                      D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
+                                                      D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
+                                                      pfloor, P.n);
         else if (ph.kind == kPhaseInternal)
-            k_internal<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs);
+            k_internal<T, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs, pfloor, P.n);
         else
             k_trsm<T><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, lxs);
     }
@@ -1152,8 +1439,12 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
 hipError_t launch_factor(const Plan &P, const DevicePlan &D, const double *Ax, hipStream_t s,
                          FactorProfile *prof)
 {
-    if (P.precision == 1) return factor_impl<float>(P, D, Ax, s, prof);
-    return factor_impl<double>(P, D, Ax, s, prof);
+    switch (P.precision) {
+    case kPrecF32: return factor_impl<float, kOpNative>(P, D, Ax, s, prof);
+    case kPrecBF16: return factor_impl<float, kOpBF16>(P, D, Ax, s, prof);
+    case kPrecF16: return factor_impl<float, kOpF16>(P, D, Ax, s, prof);
+    default: return factor_impl<double, kOpNative>(P, D, Ax, s, prof);
+    }
 }
 
 }  // namespace sym

@@ -118,6 +118,13 @@ struct Phase {
     int64_t t0, t1;     // task range in Plan::ftasks
 };
 
+// Factor precisions (sym.h: SYM_F64, SYM_F32, SYM_BF16, SYM_F16).  FP32
+// panels for all but the first; the last two scale the matrix per device
+// supernode and run the update products on 16-bit matrix cores.
+constexpr int32_t kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2, kPrecF16 = 3;
+inline bool prec_fp32_panels(int32_t p) { return p != kPrecF64; }
+inline bool prec_scaled(int32_t p) { return p == kPrecBF16 || p == kPrecF16; }
+
 constexpr int kTileRows = 64;   // T: rows per factor task tile
 constexpr int kSolveChunk = 256; // rows below the diagonal per forward-solve task
 
@@ -153,7 +160,9 @@ struct Plan {
     int32_t n = 0;
     int64_t nnzA = 0;
     int32_t B = 64;             // block width
-    int32_t precision = 0;      // 0 = f64, 1 = f32
+    int32_t precision = 0;      // kPrec*
+    double pivot_floor = 0.0;   // tau: pivots below tau times their scaled diagonal entry are
+                                // replaced by it (scaled precisions only; 0 = never)
     double analyze_ms = 0.0;
 
     // ---- ordering and column structure (permuted numbering)
@@ -252,6 +261,11 @@ struct Plan {
 
     // A -> L map (offset into L's values for every entry of A, input order)
     std::vector<int64_t> amap;
+    // for the per-supernode scaling: every entry's permuted (row, column),
+    // and the index in A of each permuted column's diagonal entry (-1 if
+    // the pattern has none)
+    std::vector<int32_t> acoord;    // 2 * nnzA
+    std::vector<int64_t> adiag;     // n
 
     // full symmetric pattern of A in the original ordering, by rows, for the
     // FP64 residual of iterative refinement: row i holds the entries

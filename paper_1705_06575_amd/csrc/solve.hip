@@ -113,22 +113,35 @@ __device__ __forceinline__ void inv_partials(const double *D, const double *vb, 
     pp[q * 64 + lane] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
+// y = D P b and x = P^T D y; D = diag(dscale) is the factor's
+// per-supernode scaling (identity when dscale is null): the factor is that
+// of D P A P^T D, so A^{-1} = P^T D (D P A P^T D)^{-1} D P.
 __global__ void k_gather(const double *__restrict__ b, const int32_t *__restrict__ perm,
-                         double *__restrict__ y, int32_t n)
+                         double *__restrict__ y, int32_t n, const double *__restrict__ dscale)
 {
     b += (int64_t)blockIdx.y * n;
     y += (int64_t)blockIdx.y * n;
+    if (dscale) dscale += (int64_t)blockIdx.y * n;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        y[i] = b[perm[i]];
+        y[i] = dscale ? b[perm[i]] * dscale[i] : b[perm[i]];
 }
 
 __global__ void k_scatter_perm(const double *__restrict__ y, const int32_t *__restrict__ perm,
-                               double *__restrict__ x, int32_t n)
+                               double *__restrict__ x, int32_t n, const double *__restrict__ dscale)
 {
     y += (int64_t)blockIdx.y * n;
     x += (int64_t)blockIdx.y * n;
+    if (dscale) dscale += (int64_t)blockIdx.y * n;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        x[perm[i]] = y[i];
+        x[perm[i]] = dscale ? y[i] * dscale[i] : y[i];
+}
+
+__global__ void k_scale(double *__restrict__ y, const double *__restrict__ dscale, int32_t n)
+{
+    y += (int64_t)blockIdx.y * n;
+    dscale += (int64_t)blockIdx.y * n;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        y[i] *= dscale[i];
 }
 
 __global__ void k_zero2(double *__restrict__ a, double *__restrict__ b, int32_t n)
@@ -140,11 +153,11 @@ __global__ void k_zero2(double *__restrict__ a, double *__restrict__ b, int32_t 
 }
 
 __global__ void k_place(const double *__restrict__ bv, const int32_t *__restrict__ bpos,
-                        double *__restrict__ y, int64_t nb)
+                        double *__restrict__ y, int64_t nb, const double *__restrict__ dscale)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb;
          k += (int64_t)gridDim.x * blockDim.x)
-        y[bpos[k]] = bv[k];
+        y[bpos[k]] = dscale ? bv[k] * dscale[bpos[k]] : bv[k];
 }
 
 constexpr int kSpinLimit = 1 << 22;     // sleeps of ~0.2 us: about a second
@@ -540,26 +553,34 @@ hipError_t static_scratch(void **ptr)
 hipError_t launch_perm_gather(const Plan &P, const DevicePlan &D, const double *b, double *y,
                               hipStream_t s)
 {
-    if (P.n > 0) k_gather<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(b, D.perm, y, P.n);
+    if (P.n > 0) k_gather<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(b, D.perm, y, P.n, D.dscale);
     return hipGetLastError();
 }
 
 hipError_t launch_perm_scatter(const Plan &P, const DevicePlan &D, const double *y, double *x,
                                hipStream_t s)
 {
-    if (P.n > 0) k_scatter_perm<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(y, D.perm, x, P.n);
+    if (P.n > 0)
+        k_scatter_perm<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(y, D.perm, x, P.n, D.dscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
+{
+    if (P.n > 0 && D.dscale) k_scale<<<dim3(grid_for(P.n), (unsigned)D.m), 256, 0, s>>>(y, D.dscale, P.n);
     return hipGetLastError();
 }
 
 hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *acc, double *out, hipStream_t s)
 {
-    return P.precision == 1 ? fwd_impl<float>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s)
+    return prec_fp32_panels(P.precision)
+               ? fwd_impl<float>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s)
                             : fwd_impl<double>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s);
 }
 
 hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
 {
-    return P.precision == 1 ? bwd_impl<float>(P, D, y, s) : bwd_impl<double>(P, D, y, s);
+    return prec_fp32_panels(P.precision) ? bwd_impl<float>(P, D, y, s) : bwd_impl<double>(P, D, y, s);
 }
 
 hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs &R,
@@ -567,8 +588,9 @@ hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs
                              hipStream_t s)
 {
     if (P.n > 0) k_zero2<<<grid_for(P.n), 256, 0, s>>>(acc, out, P.n);
-    if (nbeta > 0) k_place<<<grid_for(nbeta), 256, 0, s>>>(bv, R.bpos, acc, nbeta);
-    return P.precision == 1 ? fwd_impl<float>(P, D, R.tasks, R.slots, R.pend, acc, out, s)
+    if (nbeta > 0) k_place<<<grid_for(nbeta), 256, 0, s>>>(bv, R.bpos, acc, nbeta, D.dscale);
+    return prec_fp32_panels(P.precision)
+               ? fwd_impl<float>(P, D, R.tasks, R.slots, R.pend, acc, out, s)
                             : fwd_impl<double>(P, D, R.tasks, R.slots, R.pend, acc, out, s);
 }
 

@@ -840,6 +840,16 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         }
     }
 
+    // ----------------------- permuted coordinates of A's entries, diagonal
+    P.acoord.resize(2 * (size_t)P.nnzA);
+    P.adiag.assign((size_t)n, -1);
+    for (int32_t c = 0; c < n; ++c)
+        for (int64_t p = C.cp[c]; p < C.cp[c + 1]; ++p) {
+            P.acoord[2 * (size_t)C.src[p]] = C.ci[p];
+            P.acoord[2 * (size_t)C.src[p] + 1] = c;
+            if (C.ci[p] == c) P.adiag[c] = C.src[p];
+        }
+
     // ------------------------------------------------------ A -> L map
     P.amap.resize((size_t)P.nnzA);
     for (int32_t c = 0; c < n; ++c) {

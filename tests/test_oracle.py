@@ -352,3 +352,26 @@ def test_planted_mistakes_fail_pins(orc, monkeypatch):
         for j in range(w.n):
             Lg[g["Li"][g["Lp"][j]:g["Lp"][j + 1]], j] = g["Lx"][g["Lp"][j]:g["Lp"][j + 1]]
         assert np.linalg.norm(Lg - Lref) > 1e-6 * np.linalg.norm(Lref)
+
+
+def test_llt_residual_equals_dense_definition(orc):
+    """||L L^T - C||_F / ||C||_F written out with dense numpy matrices (the
+    full symmetric C, off-diagonal entries counted twice) equals the
+    oracle's sparse evaluation, for exact and for perturbed factors."""
+    rng = np.random.default_rng(23)
+    for t in range(20):
+        n = int(rng.integers(3, 60))
+        w = W.random_spd(n, float(rng.choice([0.05, 0.2, 0.6])), np.random.default_rng(4100 + t))
+        f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+        Cd = np.zeros((n, n))
+        for j in range(n):
+            for p in range(f["Cp"][j], f["Cp"][j + 1]):
+                Cd[f["Ci"][p], j] = Cd[j, f["Ci"][p]] = f["Cx"][p]
+        for scale in (0.0, 1e-3, 0.3):
+            Lx = f["Lx"] * (1.0 + scale * rng.standard_normal(f["Lx"].size))
+            Ld = np.zeros((n, n))
+            for j in range(n):
+                Ld[f["Li"][f["Lp"][j]:f["Lp"][j + 1]], j] = Lx[f["Lp"][j]:f["Lp"][j + 1]]
+            ref = np.linalg.norm(Ld @ Ld.T - Cd) / np.linalg.norm(Cd)
+            got = orc.llt_residual(n, f["Cp"], f["Ci"], f["Cx"], f["Lp"], f["Li"], Lx)
+            assert abs(got - ref) <= 1e-12 * max(ref, 1e-3), (n, scale, got, ref)

@@ -247,3 +247,33 @@ def test_kind_flops_partition_the_method_count(S):
             an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", block_width=B)
             kf = an.kind_flops()
             assert sum(kf.values()) == an.stat("flops")
+
+
+class _Pat:
+    """A pattern with dummy values, for the symbolic comparisons."""
+
+    def __init__(self, name, n, Ap, Ai, perm):
+        self.name, self.n, self.Ap, self.Ai, self.perm = name, n, Ap, Ai, perm
+        self.Ax = np.ones(Ai.size)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cfg", ["grid3d_7pt_64_library_nd", "grid3d_27pt_80", "batch_9pt128",
+                                 "batch_7pt24", "batch_7pt40"])
+def test_symbolic_matches_oracle_full_size(S, orc, cfg):
+    """The benchmark workloads' full patterns, bit for bit against O2 (Eq.
+    (1) with explicit sets): elimination tree, column counts, L's pattern
+    and the fundamental supernodes.  The 64^3 7-point grid in the library's
+    own nested-dissection order (the benchmark's), the 80^3 27-point grid in
+    its geometric order (the mixed-precision workload's), and the three
+    batched patterns in their grid orders."""
+    if cfg == "grid3d_7pt_64_library_nd":
+        w = W.config2(64)
+        perm = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd").get("perm")
+    elif cfg == "grid3d_27pt_80":
+        w = W.config3(80)
+        perm = w.perm
+    else:
+        n, Ap, Ai, _, perm = W.config4_batch(cfg.split("_")[1], 1)
+        w = _Pat(cfg, n, Ap, Ai, perm)
+    _check_symbolic(S, orc, w, perm)
