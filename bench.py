@@ -37,29 +37,67 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def cpu_baseline(m: int = 48):
-    """The oracle (plain C, one thread) factoring the same recipe on an m^3
-    grid with the geometric nested-dissection ordering."""
-    import oracle
-    import workloads as W
-    w = W.config2(m)
-    t0 = time.perf_counter()
-    f = oracle.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
-    dt = time.perf_counter() - t0
-    cpu = "unknown"
+def _host_cpu() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "unknown"
+
+
+def leading_sample(w, perm, Lp, Li, target_flops: float):
+    """The benchmark matrix's leading principal submatrix C[:k, :k] of
+    C = P A P^T (P: the benchmark's ordering): its Cholesky factor is
+    L[:k, :k], so factoring it is exactly the first k columns' share of the
+    benchmark's factorization (their rows below k left out).  k is the
+    largest multiple of n/64 whose flops, sum over j < k of |L_j rows < k|^2,
+    stay within target_flops.  Returns (k, flops, Ap, Ai, Ax) in the new
+    numbering (identity ordering)."""
+    import numpy as np
+    n = w.n
+    best = (0, 0.0)
+    for q in range(1, 65):
+        k = n * q // 64
+        m = Li[:Lp[k]] < k
+        cnt = np.add.reduceat(m.astype(np.int64), Lp[:k]) if k > 0 else np.zeros(0, np.int64)
+        fl = float((cnt.astype(np.float64) ** 2).sum())
+        if fl > target_flops:
+            break
+        best = (k, fl)
+    k, fl = best
+    pinv = np.empty(n, np.int64)
+    pinv[perm] = np.arange(n)
+    cols = np.repeat(np.arange(n), np.diff(w.Ap))
+    a, b = pinv[w.Ai.astype(np.int64)], pinv[cols]
+    keep = (a < k) & (b < k)
+    hi, lo, val = np.maximum(a, b)[keep], np.minimum(a, b)[keep], w.Ax[keep]
+    order = np.lexsort((hi, lo))
+    Ap = np.zeros(k + 1, np.int64)
+    np.add.at(Ap, lo + 1, 1)
+    return k, fl, np.cumsum(Ap), hi[order].astype(np.int32), val[order]
+
+
+def cpu_baseline(w, perm, Lp, Li, target_flops: float = 5e10):
+    """The oracle (plain C, one thread) on a bounded sample of the benchmark
+    workload itself: the leading principal submatrix of the 64^3 matrix in
+    the benchmark's ordering (see leading_sample), about 10-30 s of CPU
+    work."""
+    import numpy as np
+    import oracle
+    k, fl, Ap, Ai, Ax = leading_sample(w, perm, Lp, Li, target_flops)
+    t0 = time.perf_counter()
+    f = oracle.factor(k, Ap, Ai, Ax, np.arange(k, dtype=np.int32))
+    dt = time.perf_counter() - t0
+    assert f["info"] == 0 and f["flops"] == fl
     return {"value": round(f["flops"] / dt / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"column Cholesky of the same 3-D 7-point recipe on a {m}^3 grid "
-                      f"(n={w.n}, {f['flops']:.3e} flops, geometric ND), {dt:.1f} s",
-            "host_cpu": cpu, "host_threads": os.cpu_count()}
+            "sample": f"column Cholesky of the leading {k} x {k} principal submatrix of the "
+                      f"benchmark's permuted 64^3 matrix (its factor is the first {k} of "
+                      f"{w.n} columns of L, rows below {k} left out; {fl:.3e} flops), {dt:.1f} s",
+            "host_cpu": _host_cpu(), "host_threads": os.cpu_count()}
 
 
 def attainable_factor_ms(an, w) -> float:
@@ -141,6 +179,7 @@ def small_case(dev, reps: int = 10):
            "fwd_dense_us": timed(lambda: an.solve_lower(b, out=ys)),
            "full_solve_us": timed(lambda: (x.copy_(b), an.solve_(x))),
            "fwd_sparse_8_us": timed(lambda: an.solve_lower_sparse(rp, bv, out=ys)),
+           "full_solve_sparse_8_us": timed(lambda: an.solve_sparse(rp, bv, out=x)),
            "note": "latency-bound (L cache-resident); no bandwidth fraction reported"}
     assert an.status() == 0
     return res
@@ -266,6 +305,37 @@ def write_traffic(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_writ
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))
+
+
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_busy_factor_grid3d_7pt_64.json")
+
+
+def write_mfma_busy(sq_csv: str, out_path: str = MFMA_FILE):
+    """Matrix-core busy share of each factor kernel from a rocprofv3 SQ
+    counter run: SQ_VALU_MFMA_BUSY_CYCLES / (4 x SQ_BUSY_CU_CYCLES), summed
+    over the kernel's FP64 dispatches."""
+    res = {"source_sha256": _source_digest(), "kernels": {}}
+    for kern in FACTOR_KERNELS:
+        busy = sum(v for k, v in _counter_rows(sq_csv, "SQ_VALU_MFMA_BUSY_CYCLES") if kern + "<double" in k)
+        cu = sum(v for k, v in _counter_rows(sq_csv, "SQ_BUSY_CU_CYCLES") if kern + "<double" in k)
+        if cu > 0:
+            res["kernels"][kern] = {"mfma_busy": busy / (4.0 * cu)}
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+def stored_mfma_busy(kernel: str):
+    """The stored matrix-core busy share of `kernel`, or None when there is
+    none or the factor sources changed since it was measured."""
+    try:
+        with open(MFMA_FILE) as f:
+            res = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if res.get("source_sha256") != _source_digest() or kernel not in res.get("kernels", {}):
+        return None
+    return round(res["kernels"][kernel]["mfma_busy"], 4)
 
 
 def stored_traffic(kernel: str):
@@ -426,11 +496,17 @@ def main():
     ap.add_argument("--no-small-case", action="store_true", help="skip the small latency-bound case")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (byte-counter calibration)")
+    ap.add_argument("--write-mfma-busy", metavar="SQ_CSV",
+                    help="only turn a rocprofv3 SQ counter run into the stored matrix-core busy "
+                         "share of the factor kernels")
     ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                         "COPY_WRITE_CSV", "COPY_BYTES"),
                     help="only turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the stored "
                          "per-launch HBM bytes of the factor kernels")
     args = ap.parse_args()
+    if args.write_mfma_busy:
+        write_mfma_busy(args.write_mfma_busy)
+        return
     if args.write_traffic:
         a = args.write_traffic
         write_traffic(a[0], a[1], a[2], a[3], int(a[4]))
@@ -467,6 +543,9 @@ def main():
 
     flops_factor = an.stat("flops")
     nnzL = an.stat("nnzL")
+    perm_bench = an.get("perm")
+    Lp_bench = an.get("Lp") if not args.no_cpu_baseline else None
+    Li_bench = an.get("Li") if not args.no_cpu_baseline else None
     reach = rp.reach()
     colcount = an.get("colcount")
     nnzL_reach = float(colcount[reach].sum())
@@ -560,12 +639,15 @@ def main():
         "factor_frac_fp64_peak": round(flops_factor / (t_factor * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
         "sptrsv_fwd_dense_ms": round(t_fwd, 4),
         "sptrsv_fwd_dense_gbps": round(bytes_fwd / (t_fwd * 1e-3) / 1e9, 2),
+        "sptrsv_fwd_dense_frac_hbm": round(bytes_fwd / (t_fwd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "factor_attainable_ms": round(t_attain, 3),
         "factor_frac_attainable": round(t_attain / t_factor, 4),
         "sptrsv_fwd_dense_cold_ms": round(t_fwd_cold, 4),
         "sptrsv_fwd_dense_cold_gbps": round(bytes_fwd / (t_fwd_cold * 1e-3) / 1e9, 2),
         "sptrsv_fwd_sparse_ms": round(t_sparse, 4),
         "sptrsv_fwd_sparse_gbps": round(bytes_sparse / (t_sparse * 1e-3) / 1e9, 2),
+        "sptrsv_fwd_sparse_frac_hbm": round(bytes_sparse / (t_sparse * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "sptrsv_algorithmic_bytes": {"fwd_dense": bytes_fwd, "fwd_sparse": bytes_sparse},
         "full_solve_ms": round(t_solve, 4),
         "analyze_s": round(analyze_s, 3),
         "factor_kernels_ms_per_step": {k: round(v, 3) for k, v in prof_ms.items()},
@@ -574,6 +656,10 @@ def main():
                      "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
                      "traffic": stored_traffic(f"k_{dom}"),
+                     "mfma_busy": stored_mfma_busy(f"k_{dom}"),
+                     "mfma_busy_note": "matrix-core busy cycles / (4 SIMDs x busy CU cycles), "
+                                       "rocprofv3 SQ counters of the same kernel (profiles/); "
+                                       "null once the factor sources changed since",
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
                      "algorithmic_flops_per_launch": dom_flops_per_launch},
@@ -591,7 +677,7 @@ def main():
         torch.cuda.empty_cache()
         out["costmodel"] = costmodel(dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(w, perm_bench, Lp_bench, Li_bench)
     print(json.dumps(out))
 
 

@@ -86,7 +86,11 @@ typedef struct sym_opts {
                                 symbolic outputs are the fundamental ones either way. */
     int32_t pivot_floor_exp; /* SYM_BF16 / SYM_F16: tau = 2^pivot_floor_exp (-60..0); 0 = the
                                 format's default; 1 = no floor.  Ignored otherwise. */
-    int32_t reserved[6];
+    int32_t max_super_width; /* widest device supernode, 1..16384 (0 = 16384); wider ones, and
+                                ones whose w x r panel reaches 4 GiB, are cut into pieces of
+                                consecutive columns (device panels only; the reported
+                                supernodes stay the fundamental ones) */
+    int32_t reserved[5];
 } sym_opts;
 
 typedef struct sym_plan *sym_handle;
@@ -231,6 +235,16 @@ int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream);
 int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double *y_dev,
                            void *stream);
 
+/*
+ * Full solve A x = b for a sparse b: the reach-pruned forward sweep of
+ * sym_solve_lower_sparse (Section 1.1), then the backward sweep over every
+ * block (the transposed sweep's reach from a root path covers nearly all
+ * of L), then the permutation back.  bv_dev: device double[nb], values at
+ * the positions given to sym_rhs_analyze; x_dev: device double[n], original
+ * ordering (written).  Errors as sym_solve_lower_sparse.
+ */
+int sym_solve_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double *x_dev, void *stream);
+
 /* Synchronize the bound stream and return the factorization status:
  * *info = 0, or 1 + the original index of the first column whose pivot was
  * not positive (first in elimination order).  Errors: SYM_ESTATE, SYM_EHIP. */
@@ -285,6 +299,8 @@ int sym_rhs_get(sym_rhs r, int64_t *count, int32_t *cols_or_null);
 #define SYM_STAT_NSLEVELS 14      /* levels of the device supernodal elimination tree */
 #define SYM_STAT_NDSUPER 15       /* device supernodes (after amalgamation) */
 #define SYM_STAT_STORED_LOWER 16  /* lower-trapezoid entries stored (nnz(L) plus explicit zeros) */
+#define SYM_STAT_EXT_OPERAND_ENTRIES 17 /* panel entries the external-update products read, without
+                                           cache reuse: sum of (rows + columns) x inner dimension */
 int sym_stat(sym_handle h, int what, double *value);
 
 /* Per-launch timing of the factorization for measurement.  With enable != 0,

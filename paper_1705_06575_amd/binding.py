@@ -32,7 +32,7 @@ GET_DTYPE = dict(perm=np.int32, parent=np.int32, colcount=np.int64, Lp=np.int64,
                  super_feat=np.float64, task_super=np.int32, variant=np.uint8)
 STAT = dict(n=1, nnzA=2, nnzL=3, flops=4, nsuper=5, nblocks=6, nlevels=7, npairs=8,
             panel_entries=9, analyze_ms=10, sum_rows=11, nphases=12, nincidences=13,
-            nslevels=14, ndsuper=15, stored_lower=16)
+            nslevels=14, ndsuper=15, stored_lower=16, ext_operand_entries=17)
 
 
 class SymError(RuntimeError):
@@ -50,12 +50,13 @@ class sym_opts(ctypes.Structure):
                 ("nd_leaf", ctypes.c_int32),
                 ("amalgamate", ctypes.c_int32),
                 ("pivot_floor_exp", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("max_super_width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
            "sym_solve", "sym_solve_static", "sym_solve_lower", "sym_solve_upper", "sym_rhs_analyze",
-           "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_status",
+           "sym_rhs_workspace", "sym_rhs_bind", "sym_solve_lower_sparse", "sym_solve_sparse", "sym_status",
            "sym_export_factor", "sym_pivots_perturbed", "sym_get_size", "sym_get", "sym_rhs_get", "sym_stat",
            "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
            "sym_rhs_destroy", "sym_batch_create", "sym_batch_workspace", "sym_batch_bind",
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     L.sym_rhs_workspace.argtypes = [vp, ctypes.POINTER(sz)]
     L.sym_rhs_bind.argtypes = [vp, vp, sz, vp]
     L.sym_solve_lower_sparse.argtypes = [vp, vp, vp, vp, vp]
+    L.sym_solve_sparse.argtypes = [vp, vp, vp, vp, vp]
     L.sym_status.argtypes = [vp, ctypes.POINTER(i64)]
     L.sym_export_factor.argtypes = [vp, vp, vp]
     L.sym_pivots_perturbed.argtypes = [vp, ctypes.POINTER(i64)]
@@ -178,7 +180,7 @@ class Analysis:
     """
 
     def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=24,
-                 amalgamate=True, pivot_floor_exp=0):
+                 amalgamate=True, pivot_floor_exp=0, max_super_width=0):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -200,6 +202,7 @@ class Analysis:
         o.block_width = int(block_width)
         o.precision = PRECISIONS[precision]
         o.pivot_floor_exp = int(pivot_floor_exp)
+        o.max_super_width = int(max_super_width)
         o.nd_leaf = int(nd_leaf)
         o.amalgamate = int(bool(amalgamate))
         self.precision = precision
@@ -353,6 +356,17 @@ class Analysis:
         _check("sym_solve_lower_sparse", self._lib.sym_solve_lower_sparse(
             self._h, r._r, _dev_ptr(bv, "torch.float64", r.nb), _dev_ptr(y, "torch.float64", self.n), _stream()))
         return y
+
+    def solve_sparse(self, r: "RhsPlan", bv, out=None):
+        """x = A^-1 b for the sparse b (values bv at r's positions), original
+        ordering: reach-pruned forward sweep, full backward sweep."""
+        import torch
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=bv.device)
+        if r._ws is None:
+            r.bind(bv.device)
+        _check("sym_solve_sparse", self._lib.sym_solve_sparse(
+            self._h, r._r, _dev_ptr(bv, "torch.float64", r.nb), _dev_ptr(x, "torch.float64", self.n), _stream()))
+        return x
 
     PROFILE_KINDS = ("scatter", "external", "trsm", "internal")
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <stdexcept>
 #include <vector>
 
 #include "device.hpp"
@@ -26,7 +27,8 @@ struct sym_plan {
            off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
            off_parts = 0, off_pcount = 0, off_pbuf = 0, off_invb = 0,
            off_info = 0, off_dscale = 0, off_pfloor = 0, off_adiag = 0, off_acoord = 0,
-           off_dsptr = 0;
+           off_dsptr = 0, off_fss = 0, off_fsq = 0, off_bss = 0, off_bsq = 0, off_cptr = 0,
+           off_chunks = 0;
     sym::DevicePlan D;
     bool bound = false;
     bool factored = false;
@@ -50,7 +52,8 @@ struct sym_rhs_plan {
     std::vector<int32_t> bpos;       // permuted positions of b's nonzeros
     std::vector<int64_t> level_ptr;  // groups of `tasks` per nonempty level
     std::vector<int32_t> pend;       // nb: chunks of `tasks` whose rows meet each block
-    size_t ws_bytes = 0, off_tasks = 0, off_bpos = 0, off_pend = 0;
+    sym::SweepSlots slots;           // ticket slots of the pruned sweep
+    size_t ws_bytes = 0, off_tasks = 0, off_bpos = 0, off_pend = 0, off_ss = 0, off_sq = 0;
     sym::DeviceRhs R;
     bool bound = false;
 };
@@ -114,6 +117,12 @@ void layout(sym_plan *h)
     h->off_adiag = take(sc ? sizeof(int64_t) * P.adiag.size() : 0);
     h->off_acoord = take(sc ? sizeof(int32_t) * P.acoord.size() : 0);
     h->off_dsptr = take(sc ? sizeof(int32_t) * P.dsptr.size() : 0);
+    h->off_cptr = take(sizeof(int64_t) * P.cptr.size());
+    h->off_chunks = take(sizeof(sym::StageChunk) * P.chunks.size());
+    h->off_fss = take(sizeof(int32_t) * P.fwd_slots.start.size());
+    h->off_fsq = take(P.fwd_slots.quad.size());
+    h->off_bss = take(sizeof(int32_t) * P.bwd_slots.start.size());
+    h->off_bsq = take(P.bwd_slots.quad.size());
     h->ws_bytes = o;
 }
 
@@ -183,9 +192,12 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
             h->P.pivot_floor = std::ldexp(1.0, e);
         }
         rc = sym::analyze(n, Ap, Ai, o.ordering, o.perm, o.block_width ? o.block_width : 64,
-                          o.nd_leaf > 0 ? o.nd_leaf : 24, o.amalgamate != 0, h->P);
+                          o.nd_leaf > 0 ? o.nd_leaf : 24, o.amalgamate != 0,
+                          o.max_super_width ? o.max_super_width : sym::kMaxDeviceWidth, h->P);
         if (rc == SYM_OK) layout(h);
     } catch (const std::bad_alloc &) {
+        rc = SYM_ENOMEM;
+    } catch (const std::length_error &) {
         rc = SYM_ENOMEM;
     }
     if (rc != SYM_OK) {
@@ -252,6 +264,12 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.pcount = (int32_t *)(base + h->off_pcount);
     D.pbuf = base + h->off_pbuf;
     D.inv_blocks = (int32_t *)(base + h->off_invb);
+    D.cptr = (int64_t *)(base + h->off_cptr);
+    D.chunks = (sym::StageChunk *)(base + h->off_chunks);
+    D.fwd_slot_start = (int32_t *)(base + h->off_fss);
+    D.fwd_slot_quad = (uint8_t *)(base + h->off_fsq);
+    D.bwd_slot_start = (int32_t *)(base + h->off_bss);
+    D.bwd_slot_quad = (uint8_t *)(base + h->off_bsq);
     const bool sc = sym::prec_scaled(P.precision);
     D.dscale = sc ? (double *)(base + h->off_dscale) : nullptr;
     D.pfloor = sc ? (double *)(base + h->off_pfloor) : nullptr;
@@ -259,7 +277,15 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.acoord = sc ? (int32_t *)(base + h->off_acoord) : nullptr;
     D.dsptr = sc ? (int32_t *)(base + h->off_dsptr) : nullptr;
     hipError_t e = hipSuccess;
-    if (sc) {
+    e = upload(D.cptr, P.cptr.data(), sizeof(int64_t) * P.cptr.size(), s);
+    if (e == hipSuccess) e = upload(D.chunks, P.chunks.data(), sizeof(sym::StageChunk) * P.chunks.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.fwd_slot_start, P.fwd_slots.start.data(), sizeof(int32_t) * P.fwd_slots.start.size(), s);
+    if (e == hipSuccess) e = upload(D.fwd_slot_quad, P.fwd_slots.quad.data(), P.fwd_slots.quad.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.bwd_slot_start, P.bwd_slots.start.data(), sizeof(int32_t) * P.bwd_slots.start.size(), s);
+    if (e == hipSuccess) e = upload(D.bwd_slot_quad, P.bwd_slots.quad.data(), P.bwd_slots.quad.size(), s);
+    if (sc && e == hipSuccess) {
         e = upload(D.adiag, P.adiag.data(), sizeof(int64_t) * P.adiag.size(), s);
         if (e == hipSuccess) e = upload(D.acoord, P.acoord.data(), sizeof(int32_t) * P.acoord.size(), s);
         if (e == hipSuccess) e = upload(D.dsptr, P.dsptr.data(), sizeof(int32_t) * P.dsptr.size(), s);
@@ -435,6 +461,8 @@ int sym_set_variants(sym_handle h, const uint8_t *variant, int32_t count)
         sym::build_schedule(h->P);
     } catch (const std::bad_alloc &) {
         return SYM_ENOMEM;
+    } catch (const std::length_error &) {
+        return SYM_ENOMEM;
     }
     layout(h);
     h->bound = false;
@@ -576,6 +604,9 @@ int sym_rhs_analyze(sym_handle h, int64_t nb, const int32_t *bi, sym_rhs *out)
         r->off_tasks = take(sizeof(sym::SolveTask) * r->tasks.size());
         r->off_bpos = take(sizeof(int32_t) * r->bpos.size());
         r->off_pend = take(sizeof(int32_t) * r->pend.size());
+        r->slots = sym::sweep_slots(P, r->tasks, true);
+        r->off_ss = take(sizeof(int32_t) * r->slots.start.size());
+        r->off_sq = take(r->slots.quad.size());
         r->ws_bytes = std::max<size_t>(o, 256);
     } catch (const std::bad_alloc &) {
         delete r;
@@ -602,8 +633,13 @@ int sym_rhs_bind(sym_rhs r, void *dev_ws, size_t bytes, void *stream)
     r->R.bpos = (int32_t *)(base + r->off_bpos);
     r->R.pend = (int32_t *)(base + r->off_pend);
     r->R.ntasks = (int64_t)r->tasks.size();
-    r->R.slots = sym::sweep_slots(r->h->P, r->tasks, true);
+    r->R.slot_start = (int32_t *)(base + r->off_ss);
+    r->R.slot_quad = (uint8_t *)(base + r->off_sq);
+    r->R.nslots = r->slots.count();
     hipError_t e = upload(r->R.tasks, r->tasks.data(), sizeof(sym::SolveTask) * r->tasks.size(), s);
+    if (e == hipSuccess)
+        e = upload(r->R.slot_start, r->slots.start.data(), sizeof(int32_t) * r->slots.start.size(), s);
+    if (e == hipSuccess) e = upload(r->R.slot_quad, r->slots.quad.data(), r->slots.quad.size(), s);
     if (e == hipSuccess) e = upload(r->R.bpos, r->bpos.data(), sizeof(int32_t) * r->bpos.size(), s);
     if (e == hipSuccess) e = upload(r->R.pend, r->pend.data(), sizeof(int32_t) * r->pend.size(), s);
     if (e != hipSuccess) return SYM_EHIP;
@@ -622,6 +658,23 @@ int sym_solve_lower_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double
     if (sym::launch_fwd_sparse(h->P, h->D, r->R, (int64_t)r->bpos.size(), bv_dev, h->D.vec, y_dev,
                                s) != hipSuccess)
         return SYM_EHIP;
+    return SYM_OK;
+}
+
+int sym_solve_sparse(sym_handle h, sym_rhs r, const double *bv_dev, double *x_dev, void *stream)
+{
+    if (!h || !r || r->h != h || (!x_dev && h->P.n) || (!bv_dev && !r->bpos.empty()))
+        return SYM_EINVAL;
+    if (!h->bound || !h->factored || !r->bound) return SYM_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
+    if (h->P.n == 0) return SYM_OK;
+    double *y = h->D.vec2;
+    if (sym::launch_fwd_sparse(h->P, h->D, r->R, (int64_t)r->bpos.size(), bv_dev, h->D.vec, y, s) !=
+        hipSuccess)
+        return SYM_EHIP;
+    if (sym::launch_bwd(h->P, h->D, y, s) != hipSuccess) return SYM_EHIP;
+    if (sym::launch_perm_scatter(h->P, h->D, y, x_dev, s) != hipSuccess) return SYM_EHIP;
     return SYM_OK;
 }
 
@@ -784,6 +837,7 @@ int sym_stat(sym_handle h, int what, double *v)
     case SYM_STAT_NINCIDENCES: *v = (double)P.incs.size(); break;
     case SYM_STAT_NSLEVELS: *v = P.nslevels; break;
     case SYM_STAT_NDSUPER: *v = P.nds; break;
+    case SYM_STAT_EXT_OPERAND_ENTRIES: *v = P.ext_operand_entries; break;
     case SYM_STAT_STORED_LOWER: {
         double st = 0;
         for (int32_t r = 0; r < P.nds; ++r) {

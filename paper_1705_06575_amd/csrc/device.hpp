@@ -28,6 +28,8 @@ struct DevicePlan {
     int64_t *wptr = nullptr;        // 4*tasks+1: wavefront item ranges
     WaveItem *witems = nullptr;     // small incidences per wavefront
     uint8_t *wmap = nullptr;        // their tile-relative rows and columns
+    int64_t *cptr = nullptr;        // tasks+1: staged chunk ranges
+    StageChunk *chunks = nullptr;   // staged chunks of the staged tasks
     int32_t *level_blocks = nullptr;// nb, grouped by level
     int64_t *amap = nullptr;        // nnzA
     int32_t *perm = nullptr;        // n
@@ -59,6 +61,10 @@ struct DevicePlan {
     int32_t *pend = nullptr;        // nb: live counters
     int32_t *done = nullptr;        // nb: blocks whose backward solve is final
     int32_t *ticket = nullptr;      // next task of a running sweep
+    int32_t *fwd_slot_start = nullptr;  // ticket slots of the dense forward sweep
+    uint8_t *fwd_slot_quad = nullptr;
+    int32_t *bwd_slot_start = nullptr;  // ticket slots of the backward sweep
+    uint8_t *bwd_slot_quad = nullptr;
     // per-supernode scaling (scaled precisions; null otherwise): the factor
     // is that of D P A P^T D, D = diag(dscale) in permuted numbering
     double *dscale = nullptr;       // n (per instance)
@@ -74,7 +80,9 @@ struct DeviceRhs {
     int32_t *bpos = nullptr;        // nb_rhs: permuted positions of b's nonzeros
     int32_t *pend = nullptr;        // nb: initial counters of the pruned forward sweep
     int64_t ntasks = 0;
-    SweepSlots slots;               // ticket slots of the pruned forward sweep
+    int32_t *slot_start = nullptr;  // ticket slots of the pruned forward sweep
+    uint8_t *slot_quad = nullptr;
+    int64_t nslots = 0;
 };
 
 // Optional per-launch event pairs for measurement: ev[2*i], ev[2*i+1]

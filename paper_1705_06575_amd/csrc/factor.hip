@@ -1001,6 +1001,184 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
     }
 }
 
+// ---- staged products
+//
+// A staged tile runs its incidences as one stream of chunks (at most
+// kStageK inner indices of one incidence each; StageChunk).  Per chunk the
+// whole workgroup stages K's product rows for the chunk's inner indices in
+// LDS (thread (r, q) loads row r at inner indices q, q + 4, q + 8, q + 12),
+// so each row value is read from memory once per tile; then wavefront v
+// multiplies all product rows with the product columns landing in its 16
+// tile columns (its slice of K's column rows, read by its own lanes) and
+// accumulates over the incidence's chunks; after the incidence's last chunk
+// it subtracts the product from its own tile columns.  Wavefronts write
+// disjoint columns, so no barrier separates incidences; one barrier per
+// chunk guards the double-buffered stage.  The next chunk's rows and
+// columns are loaded while the current one is multiplied.
+
+// A chunk record, read as whole dwords (scalar registers).
+struct Chunk {
+    int64_t valoff;
+    int ld, b0, a0, kc, nI, nJ, nk, last, jlo, jhi;
+    uint32_t map;
+};
+
+__device__ __forceinline__ Chunk load_chunk_rec(const StageChunk *__restrict__ ch, int64_t i, int wave)
+{
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(ch + i);
+    uint32_t x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = d[u];
+    Chunk c;
+    c.valoff = (int64_t)(((uint64_t)x[1] << 32) | x[0]);
+    c.ld = (int)x[2];
+    c.b0 = (int)x[3];
+    c.a0 = (int)x[4];
+    c.map = x[5];
+    c.kc = (int)(int16_t)(x[6] & 0xffffu);
+    c.nI = (int)((x[6] >> 16) & 0xffu);
+    c.nJ = (int)(x[6] >> 24);
+    c.nk = (int)(x[7] & 0x7fu);
+    c.last = (int)((x[7] >> 7) & 1u);
+    const int j1 = (int)((x[7] >> 8) & 0xffu), j2 = (int)((x[7] >> 16) & 0xffu), j3 = (int)(x[7] >> 24);
+    c.jlo = wave == 0 ? 0 : wave == 1 ? j1 : wave == 2 ? j2 : j3;
+    c.jhi = wave == 0 ? j1 : wave == 1 ? j2 : wave == 2 ? j3 : c.nJ;
+    return c;
+}
+
+// This thread's four staged values of chunk c: row r = lane, inner indices
+// q + 4 j (q = wavefront); zero outside the rows and the chunk (addresses
+// clamped into them).
+template <typename T>
+__device__ __forceinline__ void stage_load(T (&va)[4], const T *__restrict__ Lx, const Chunk &c)
+{
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const T *LK = Lx + c.valoff;
+    const int rr = min(r, c.nI - 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = q + 4 * j;
+        const T x = LK[(int64_t)(c.kc + min(k, c.nk - 1)) * c.ld + c.b0 + rr];
+        va[j] = (r < c.nI && k < c.nk) ? x : T(0);
+    }
+}
+
+// This lane's column operand of chunk c for its wavefront: product column
+// jlo + lane % 16 (clamped) at inner index 4 s + lane / 16, s < 4, zero
+// past the chunk.
+template <typename T>
+__device__ __forceinline__ void stage_cols(T (&vb)[4], const T *__restrict__ Lx, const Chunk &c)
+{
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const T *LK = Lx + c.valoff;
+    const int j = c.jlo + min(li, max(c.jhi - c.jlo, 1) - 1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + lk;
+        const T x = LK[(int64_t)(c.kc + min(k, c.nk - 1)) * c.ld + c.a0 + min(j, c.nJ - 1)];
+        vb[s] = k < c.nk ? x : T(0);
+    }
+}
+
+// The tile rows (lane i: product row i) and this lane's tile column of the
+// incidence of chunk c.
+__device__ __forceinline__ void stage_maps(int &lr, int &cc, const uint8_t *__restrict__ imap, const Chunk &c)
+{
+    const int lane = threadIdx.x & 63, li = lane & 15;
+    const uint8_t *mp = imap + c.map;
+    lr = mp[min(lane, c.nI - 1)];
+    cc = mp[c.nI + min(c.jlo + li, c.nJ - 1)];
+}
+
+template <typename T, int OP>
+__device__ __forceinline__ void staged_products(T *C, T (*As)[kStageK][64], const StageChunk *__restrict__ ch,
+                                                int64_t c0, int64_t c1, const uint8_t *__restrict__ imap,
+                                                const T *__restrict__ Lx, int r0, int nr, int w)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (c0 >= c1) return;
+    // X: the chunk being multiplied (staged in As[buf]); Y: the next one
+    Chunk X = load_chunk_rec(ch, c0, wave);
+    T va[4], vb[4], vbn[4];
+    stage_load(va, Lx, X);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) As[0][(tid >> 6) + 4 * j][lane] = va[j];
+    stage_cols(vb, Lx, X);
+    int lr = 0, cc = 0, lrn = 0, ccn = 0;
+    if (X.last) stage_maps(lr, cc, imap, X);
+    int64_t i = c0;
+    Chunk Y = load_chunk_rec(ch, min(i + 1, c1 - 1), wave);
+    __syncthreads();
+    typename Mfma<T>::acc_t acc[4] = {};
+    for (;;) {
+        const int buf = (int)(i - c0) & 1;
+        const bool more = i + 1 < c1;
+        // the next chunk's rows, columns and (at its incidence's end) maps
+        if (more) {
+            stage_load(va, Lx, Y);
+            stage_cols(vbn, Lx, Y);
+            if (Y.last) stage_maps(lrn, ccn, imap, Y);
+        }
+        const Chunk Z = load_chunk_rec(ch, min(i + 2, c1 - 1), wave);
+        // multiply X: this wavefront's columns with every product row
+        const int nrb = (X.nI + 15) >> 4;
+        if (X.jhi > X.jlo) {
+            if constexpr (OP == kOpNative) {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    if (4 * s2 < X.nk) {
+#pragma unroll
+                        for (int m = 0; m < 4; ++m)
+                            if (m < nrb) acc[m] = Mfma<T>::mma(As[buf][4 * s2 + lk][16 * m + li], vb[s2], acc[m]);
+                    }
+                }
+            } else {
+                const float b4[4] = {vb[0], vb[1], vb[2], vb[3]};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (m < nrb) {
+                        const float a4[4] = {As[buf][lk][16 * m + li], As[buf][4 + lk][16 * m + li],
+                                             As[buf][8 + lk][16 * m + li], As[buf][12 + lk][16 * m + li]};
+                        acc[m] = mma_pack<OP>(a4, b4, acc[m]);
+                    }
+                }
+            }
+        }
+        if (X.last) {
+            // subtract the finished product from this wavefront's tile columns
+            const int nc = X.jhi - X.jlo;
+            const bool vc = li < nc && cc < w;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (m < nrb) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * m + Mfma<T>::row(lane, v);
+                        const int R = __shfl(lr, row);
+                        if (vc && row < X.nI && R < nr && r0 + R >= cc) C[cc * LDC + R] -= acc[m][v];
+                    }
+                }
+                acc[m] = typename Mfma<T>::acc_t{};
+            }
+        }
+        if (!more) break;
+        // stage the next chunk in the other buffer (last read before the
+        // previous barrier), then let every wavefront see it
+#pragma unroll
+        for (int j = 0; j < 4; ++j) As[buf ^ 1][(tid >> 6) + 4 * j][lane] = va[j];
+        __syncthreads();
+        ++i;
+        X = Y;
+        Y = Z;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) vb[s2] = vbn[s2];
+        lr = lrn;
+        cc = ccn;
+    }
+}
+
 template <typename T, bool COOP, int OP>
 __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tasks,
                                                  const int64_t *__restrict__ iptr,
@@ -1017,13 +1195,17 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
                                                  const PartDesc *__restrict__ parts,
                                                  int32_t *pcount, T *pbuf, int32_t nsplit,
                                                  int64_t npartial, const double *__restrict__ pfloor,
-                                                 int32_t n)
+                                                 int32_t n, const int64_t *__restrict__ cptr,
+                                                 const StageChunk *__restrict__ chunks)
 {
     const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
     // the tile, in the panels' precision; FP64-sized so that a fused
     // diagonal factorization can widen it in place
     __shared__ double Cbuf[64 * LDC];
     T *C = reinterpret_cast<T *>(Cbuf);
+    // operand staging of the cooperative and the staged products (one or
+    // the other per tile)
+    __shared__ double stage_mem[2 * kStageK * 64];
     Lx += blockIdx.y * lx_stride;
     info += 4 * blockIdx.y;
     pcount += (int64_t)blockIdx.y * nsplit;
@@ -1052,10 +1234,13 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     __syncthreads();
 
     int64_t q = iptr[blockIdx.x];
-    if constexpr (COOP && OP == kOpNative) {
+    if (tk.flags & kStaged) {
+        staged_products<T, OP>(C, reinterpret_cast<T(*)[kStageK][64]>(stage_mem), chunks, cptr[blockIdx.x],
+                               cptr[blockIdx.x + 1], imap, (const T *)Lx, r0, nr, w);
+    } else if constexpr (COOP && OP == kOpNative) {
         constexpr int KC = 8;   // inner indices per staged chunk of the cooperative product
-        __shared__ T As[2][KC][64];
-        __shared__ T Bs[2][KC][64];
+        T(*As)[KC][64] = reinterpret_cast<T(*)[KC][64]>(stage_mem);
+        T(*Bs)[KC][64] = reinterpret_cast<T(*)[KC][64]>(stage_mem + KC * 64 * 2 * sizeof(T) / sizeof(double));
         const int64_t qb = ibig[blockIdx.x];
         for (; q < qb; ++q) {
             const Incidence in = incs[q];
@@ -1066,8 +1251,8 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
             coop_product<T, KC>(C, As, Bs, s_rel, in, imap, Lx, r0, nr, w);
         }
     } else if constexpr (COOP) {
-        __shared__ uint64_t Ap[2][4][64];
-        __shared__ uint64_t Bp[2][4][64];
+        uint64_t(*Ap)[4][64] = reinterpret_cast<uint64_t(*)[4][64]>(stage_mem);
+        uint64_t(*Bp)[4][64] = reinterpret_cast<uint64_t(*)[4][64]>(stage_mem + 2 * 4 * 64);
         const int64_t qb = ibig[blockIdx.x];
         for (; q < qb; ++q) {
             const Incidence in = incs[q];
@@ -1411,13 +1596,13 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
                                                      D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
                                                      D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                      D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
-                                                     pfloor, P.n);
+                                                     pfloor, P.n, D.cptr + ph.t0, D.chunks);
         else if (ph.kind == kPhaseExternal)
             k_external<T, false, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                       D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
                                                       D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                       D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
-                                                      pfloor, P.n);
+                                                      pfloor, P.n, D.cptr + ph.t0, D.chunks);
         else if (ph.kind == kPhaseInternal)
             k_internal<T, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs, pfloor, P.n);
         else

@@ -75,7 +75,28 @@ struct WaveItem {       // 32 bytes, device-visible
     uint8_t nI, nJ;
 };
 
+// One chunk of a staged external-update product (a tile's incidence
+// split into runs of at most kStageK inner indices): the whole workgroup
+// stages K's rows [b0, b0 + nI) of the chunk's inner indices in LDS once;
+// wavefront v multiplies them with the product columns that land in its 16
+// tile columns, [jw[v-1], jw[v]) (jw[-1] = 0, jw[3] = nJ).  map: byte
+// offset in imap of the incidence's nI tile rows and nJ tile columns.
+struct StageChunk {     // 32 bytes, device-visible
+    int64_t valoff;     // K's panel offset
+    int32_t ld;         // K's leading dimension
+    int32_t b0;         // K's local row of the first product row
+    int32_t a0;         // K's local row of the first product column
+    uint32_t map;
+    int16_t kc;         // first inner index of the chunk
+    uint8_t nI, nJ;
+    uint8_t nk_last;    // inner indices in the chunk (1..kStageK); bit 7: the incidence's last chunk
+    uint8_t jw[3];
+};
+constexpr int kStageK = 16;
+constexpr int32_t kStaged = 4;      // Task flag: the tile's products run as staged chunks
+
 static_assert(sizeof(Incidence) == 40, "Incidence layout is shared with the device");
+static_assert(sizeof(StageChunk) == 32, "StageChunk layout is shared with the device");
 static_assert(sizeof(WaveItem) == 32, "WaveItem layout is shared with the device");
 static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
@@ -102,13 +123,16 @@ struct PartDesc {       // 16 bytes, device-visible
 };
 static_assert(sizeof(PartDesc) == 16, "PartDesc layout is shared with the device");
 
-// Kernel variant of a target supernode's external update: an incidence is
-// "large" -- multiplied by the whole workgroup through LDS -- when its
-// product has at least kVariantLarge[v] rows, columns and inner indices;
-// the others run as per-wavefront items.  Variant 0 puts every incidence on
-// the per-wavefront path, 1 (the default) uses 64, 2 uses 32.
-constexpr int kVariants = 3;
-constexpr int32_t kVariantLarge[kVariants] = {1 << 30, 64, 32};
+// Kernel variant of a target supernode's external update.  Variants 0-2:
+// an incidence is "large" -- multiplied by the whole workgroup through LDS
+// -- when its product has at least kVariantLarge[v] rows, columns and inner
+// indices; the others run as per-wavefront items (variant 0 puts every
+// incidence there, 1 uses 64, 2 uses 32).  Variant 3: every incidence runs
+// as staged chunks (StageChunk): its rows are read once per tile, instead
+// of once per wavefront whose columns it meets.
+constexpr int kVariants = 4;
+constexpr int32_t kVariantLarge[kVariants] = {1 << 30, 64, 32, 0};
+constexpr uint8_t kVariantStaged = 3;
 constexpr int kSuperFeatures = 8;   // features of a device supernode, see Plan::sfeat
 
 // One kernel launch of the factorization.
@@ -129,23 +153,25 @@ constexpr int kTileRows = 64;   // T: rows per factor task tile
 constexpr int kSolveChunk = 256; // rows below the diagonal per forward-solve task
 
 // Ticket slots of a persistent sweep.  A workgroup takes one slot per
-// ticket: tasks [0, t1) go b1 to a slot, tasks [t1, t2) one to a slot and
-// tasks [t2, n) b2 to a slot (the last slot may hold fewer).  Runs of wide
-// levels (many independent tasks) are claimed in groups, so that the one
-// ticket counter does not serialize them; the chain of narrow levels keeps
-// one task per slot.  Slots are taken in task order and a task waits only
-// on tasks before it, so a slot's tasks run in order without deadlock.
+// ticket and runs the slot's tasks [start[s], start[s + 1]): either in
+// order, by the whole workgroup, or -- a quad slot -- one task per
+// wavefront, all at once (the blocks of a quad's tasks are narrow: at most
+// kWaveCols columns and kWaveRows rows below them, so one wavefront holds a
+// task).  Consecutive narrow tasks form quads wherever they occur; in the
+// run of wide levels (many independent tasks) the other tasks go up to
+// kSlotGroup to a slot, so that the one ticket counter does not serialize
+// them; elsewhere they keep one task per slot.  Slots are taken in task
+// order and a task waits only on tasks before it (in earlier slots, or in
+// the same quad, whose wavefronts run concurrently), so no wait is circular.
 struct SweepSlots {
-    int64_t n = 0, t1 = 0, t2 = 0;
-    int32_t b1 = 1, b2 = 1;
+    std::vector<int32_t> start;     // slots + 1
+    std::vector<uint8_t> quad;      // per slot: 1 = one task per wavefront
+    int64_t count() const { return (int64_t)quad.size(); }
 };
 constexpr int32_t kSlotGroup = 4;      // tasks per slot in a wide level
 constexpr int64_t kWideLevel = 2048;   // tasks that make a level wide
-
-inline int64_t slot_count(const SweepSlots &S)
-{
-    return S.t1 / S.b1 + (S.t2 - S.t1) + (S.n - S.t2 + S.b2 - 1) / S.b2;
-}
+constexpr int32_t kWaveCols = 16;      // widest block of a wavefront task
+constexpr int32_t kWaveRows = 64;      // most rows below a wavefront task's block
 
 struct SolveTask {      // 16 bytes: one chunk of one block in a sweep
     int32_t J;
@@ -253,11 +279,19 @@ struct Plan {
     std::vector<int64_t> wptr;      // 4 * ftasks.size() + 1
     std::vector<WaveItem> witems;
     std::vector<uint8_t> wmap;
+    // staged tasks: chunks [cptr[q], cptr[q + 1]) of task q
+    std::vector<int64_t> cptr;      // ftasks.size() + 1
+    std::vector<StageChunk> chunks;
     // arithmetic of each launch kind by the method's count (lower-triangle
     // products, one flop per multiply, add, divide and square root):
     // [0] scatter (none), [1] external, [2] trsm, [3] internal; the four sum
     // to `flops`.
     double kind_flops[4] = {0, 0, 0, 0};
+    // operand entries the external-update products read, summed over the
+    // incidences and per-wavefront items of the schedule ((rows + columns)
+    // x inner dimension each): the external update's panel reads without
+    // any cache reuse
+    double ext_operand_entries = 0.0;
 
     // A -> L map (offset into L's values for every entry of A, input order)
     std::vector<int64_t> amap;
@@ -276,8 +310,14 @@ struct Plan {
 };
 
 // Analysis entry point (symbolic.cpp).  Returns SYM_OK or a SYM_E* code.
+// Device supernodes are at most kMaxDeviceWidth columns wide (and narrower
+// where w * r * 8 bytes would reach 4 GiB): widths are 16-bit fields of the
+// incidence records, panel offsets 32-bit byte offsets in the kernels.
+constexpr int32_t kMaxDeviceWidth = 16384;
+
 int analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, int ordering,
-            const int32_t *user_perm, int block_width, int nd_leaf, bool relax, Plan &P);
+            const int32_t *user_perm, int block_width, int nd_leaf, bool relax, int max_width,
+            Plan &P);
 
 // Factor schedule for the plan's current svariant (symbolic.cpp).
 void build_schedule(Plan &P);
@@ -298,5 +338,8 @@ void reach_etree(const Plan &P, const std::vector<int32_t> &beta, std::vector<in
 // with bottom_first the leading run of wide levels is grouped, otherwise
 // the trailing one.
 SweepSlots sweep_slots(const Plan &P, const std::vector<SolveTask> &tasks, bool bottom_first);
+
+// Whether a block's sweep tasks fit one wavefront.
+inline bool wave_task_block(const BlockDesc &d) { return d.w <= kWaveCols && d.r - d.w <= kWaveRows; }
 
 }  // namespace sym

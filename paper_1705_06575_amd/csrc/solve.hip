@@ -238,20 +238,103 @@ __device__ __forceinline__ int next_ticket(int32_t *ticket, int *s_t, int nslots
     return t < nslots ? t : -1;
 }
 
-// Tasks [a, b) of ticket slot s.
-__device__ __forceinline__ void slot_tasks(const SweepSlots &S, int64_t s, int64_t &a, int64_t &b)
+// Value of v in lane `src` of the wavefront (src wave-uniform).
+__device__ __forceinline__ double wave_bcast(double v, int src)
 {
-    const int64_t s1 = S.t1 / S.b1, s2 = s1 + (S.t2 - S.t1);
-    if (s < s1) {
-        a = s * S.b1;
-        b = a + S.b1;
-    } else if (s < s2) {
-        a = S.t1 + (s - s1);
-        b = a + 1;
-    } else {
-        a = S.t2 + (s - s2) * S.b2;
-        b = min(S.n, a + S.b2);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One wavefront spins until *p == 0 (every lane reads the same word).
+__device__ __forceinline__ bool wave_wait_zero(int32_t *p, int32_t *err)
+{
+    int it = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (++it > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
     }
+    return true;
+}
+
+// One wavefront spins until done[tgt[q]] != 0 for every q in [q0, q1).
+__device__ __forceinline__ bool wave_wait_all_set(const int32_t *done, const int32_t *__restrict__ tgt,
+                                                  int64_t q0, int64_t q1, int32_t *err)
+{
+    const int lane = threadIdx.x & 63;
+    int it = 0;
+    for (;;) {
+        bool ready = true;
+        for (int64_t q = q0 + lane; q < q1; q += 64)
+            ready = ready && __hip_atomic_load(&done[tgt[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        if (__all(ready)) return true;
+        if (++it > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+// Forward task of a narrow block (at most kWaveCols columns and kWaveRows
+// rows below them: one chunk) by one wavefront, with no workgroup
+// barrier: lane i < w holds row i of the diagonal block's inverse, lane l
+// the block's row w + l below it.  As the workgroup task: wait for the
+// block's counter, y_J = L_JJ^{-1} acc_J (columns from c0), the rows below
+// take their products by atomic adds, then the counters of the blocks
+// owning those rows drop.  False if the wait ran out.
+template <typename T>
+__device__ __forceinline__ bool wave_fwd_task(const SolveTask &tk, const BlockDesc &J,
+                                              const T *__restrict__ L, const int32_t *__restrict__ rows,
+                                              const int64_t *__restrict__ tptr,
+                                              const int32_t *__restrict__ tgt, int32_t *pend,
+                                              double *acc, double *__restrict__ out, int32_t *err)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = J.w, c0 = tk.c0;
+    const int64_t ld = J.ld;
+    // row il of the inverse: entries j < il, stored at (j, il); the diagonal L_ii
+    const int il = min(lane, w - 1);
+    const T *Lc = L + (int64_t)il * ld;
+    double inv[kWaveCols];
+#pragma unroll
+    for (int j = 0; j < kWaveCols; ++j) {
+        const T val = Lc[min(j, il)];
+        inv[j] = j < il ? (double)val : 0.0;
+    }
+    const double dii = (double)Lc[il];
+    const int ir = w + lane;
+    const bool has_row = ir < J.r;
+    const int ic = has_row ? ir : w - 1;
+    const int32_t row = rows[J.rowoff + ic];
+    double lv[kWaveCols];
+#pragma unroll
+    for (int k = 0; k < kWaveCols; ++k) {
+        const T val = L[(int64_t)min(k, w - 1) * ld + ic];
+        lv[k] = k < w ? (double)val : 0.0;
+    }
+    if (!wave_wait_zero(&pend[tk.J], err)) return false;
+    const bool mine = lane >= c0 && lane < w;
+    const double v = mine ? coherent_load(&acc[J.col0 + lane]) : 0.0;
+    double y = v / dii;
+#pragma unroll
+    for (int j = 0; j < kWaveCols; ++j) y = fma(inv[j], wave_bcast(v, j), y);
+    y = mine ? y : 0.0;
+    if (mine) out[J.col0 + lane] = y;
+    // the cross-lane reads run with every lane active (a lane outside a
+    // branch does not keep its register for the others to read)
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kWaveCols; ++k) s4[k & 3] = fma(lv[k], wave_bcast(y, k), s4[k & 3]);
+    if (has_row) atomicAdd(&acc[row], -((s4[0] + s4[1]) + (s4[2] + s4[3])));
+    __builtin_amdgcn_s_waitcnt(0);          // this wavefront's additions have completed
+    for (int64_t q = tptr[tk.list] + lane; q < tptr[tk.list + 1]; q += 64)
+        __hip_atomic_fetch_add(&pend[tgt[q]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
 }
 
 // Forward sweep, one persistent launch.  acc: right-hand side plus the
@@ -259,7 +342,9 @@ __device__ __forceinline__ void slot_tasks(const SweepSlots &S, int64_t s, int64
 // counter is zero, atomically updated for the rows below); out: solved
 // values of the blocks' columns.
 template <typename T>
-__global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ tasks, SweepSlots S, int nslots,
+__global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ tasks,
+                                               const int32_t *__restrict__ slot_start,
+                                               const uint8_t *__restrict__ slot_quad, int nslots,
                                                const int64_t *__restrict__ tptr,
                                                const int32_t *__restrict__ tgt,
                                                int32_t *__restrict__ pend, int32_t *ticket,
@@ -284,8 +369,19 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
     for (;;) {
         const int sl = next_ticket(ticket, &s_t, nslots, err);
         if (sl < 0 || s_abort) break;
-        int64_t ta, tb;
-        slot_tasks(S, sl, ta, tb);
+        const int64_t ta = slot_start[sl], tb = slot_start[sl + 1];
+        if (slot_quad[sl]) {
+            // one narrow task per wavefront; the next ticket's barrier joins them
+            const int64_t t = ta + (tid >> 6);
+            if (t < tb) {
+                const SolveTask tk = tasks[t];
+                const BlockDesc J = blk[tk.J];
+                if (!wave_fwd_task(tk, J, Lx + J.valoff, rows, tptr, tgt, pend, acc, out, err) &&
+                    (tid & 63) == 0)
+                    s_abort = 1;
+            }
+            continue;
+        }
         for (int64_t t = ta; t < tb; ++t) {
         __syncthreads();                    // the previous task's LDS reads are done
         const SolveTask tk = tasks[t];
@@ -346,11 +442,73 @@ __global__ __launch_bounds__(NT, 3) void k_fwd_df(const SolveTask *__restrict__ 
     }
 }
 
+// Backward task of a narrow block by one wavefront: the block's single
+// chunk (at most kWaveRows rows below it) or, for a block with no rows
+// below, its diagonal solve alone.  Lane l holds row w + l below the block,
+// lane j < w column j of the transposed inverse.  After the owners of its
+// rows are final: x_J = L_JJ^{-T} (x_J - L_offdiag^T x[rows]), the column
+// sums over the rows reduced across the wavefront (no other task touches
+// x_J, so no atomic adds are needed), then J is marked final.
+template <typename T>
+__device__ __forceinline__ bool wave_bwd_task(const SolveTask &tk, const BlockDesc &J,
+                                              const T *__restrict__ L, const int32_t *__restrict__ rows,
+                                              const int64_t *__restrict__ tptr,
+                                              const int32_t *__restrict__ tgt, int32_t *done, double *x,
+                                              int32_t *err)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = J.w;
+    const int64_t ld = J.ld;
+    // column il of L_JJ^{-T}: (L_JJ^{-1})_{i il} for i > il, stored at (il, i)
+    const int il = min(lane, w - 1);
+    double invT[kWaveCols];
+#pragma unroll
+    for (int i = 0; i < kWaveCols; ++i) {
+        const T val = L[(int64_t)min(i, w - 1) * ld + il];
+        invT[i] = (i > il && i < w) ? (double)val : 0.0;
+    }
+    const double djj = (double)L[(int64_t)il * ld + il];
+    const int ir = w + lane;
+    const bool has_row = tk.chunk >= 0 && ir < J.r;
+    const int ic = has_row ? ir : w - 1;
+    const int32_t row = rows[J.rowoff + ic];
+    double lv[kWaveCols];
+#pragma unroll
+    for (int k = 0; k < kWaveCols; ++k) {
+        const T val = L[(int64_t)min(k, w - 1) * ld + ic];
+        lv[k] = k < w ? (double)val : 0.0;
+    }
+    if (tk.chunk >= 0 && !wave_wait_all_set(done, tgt, tptr[tk.list], tptr[tk.list + 1], err))
+        return false;
+    const double xr = has_row ? coherent_load(&x[row]) : 0.0;
+    double part[kWaveCols];
+#pragma unroll
+    for (int k = 0; k < kWaveCols; ++k) part[k] = lv[k] * xr;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < kWaveCols; ++k) part[k] += __shfl_xor(part[k], off);
+    double pj = 0.0;
+#pragma unroll
+    for (int k = 0; k < kWaveCols; ++k) pj = lane == k ? part[k] : pj;
+    const bool mine = lane < w;
+    const double v = mine ? coherent_load(&x[J.col0 + lane]) - pj : 0.0;
+    double xo = v / djj;
+#pragma unroll
+    for (int i = 0; i < kWaveCols; ++i) xo = fma(invT[i], wave_bcast(v, i), xo);
+    if (mine) coherent_store(&x[J.col0 + lane], xo);
+    __builtin_amdgcn_s_waitcnt(0);          // the block's values have completed
+    if (lane == 0) __hip_atomic_store(&done[tk.J], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 // Backward sweep, one persistent launch over the tasks in ticket order
 // (levels from the top; per level the off-diagonal chunks, then the
 // diagonal solves).  x holds y on entry and the solution on exit.
 template <typename T>
-__global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ tasks, SweepSlots S, int nslots,
+__global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ tasks,
+                                               const int32_t *__restrict__ slot_start,
+                                               const uint8_t *__restrict__ slot_quad, int nslots,
                                                const int64_t *__restrict__ tptr,
                                                const int32_t *__restrict__ tgt,
                                                int32_t *__restrict__ pend, int32_t *done,
@@ -377,8 +535,18 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
     for (;;) {
         const int sl = next_ticket(ticket, &s_t, nslots, err);
         if (sl < 0 || s_abort) break;
-        int64_t ta, tb;
-        slot_tasks(S, sl, ta, tb);
+        const int64_t ta = slot_start[sl], tb = slot_start[sl + 1];
+        if (slot_quad[sl]) {
+            // one narrow block per wavefront; the next ticket's barrier joins them
+            const int64_t t = ta + wave;
+            if (t < tb) {
+                const SolveTask tk = tasks[t];
+                const BlockDesc J = blk[tk.J];
+                if (!wave_bwd_task(tk, J, Lx + J.valoff, rows, tptr, tgt, done, x, err) && lane == 0)
+                    s_abort = 1;
+            }
+            continue;
+        }
         for (int64_t t = ta; t < tb; ++t) {
         __syncthreads();                    // the previous task's LDS reads are done
         const SolveTask tk = tasks[t];
@@ -501,28 +669,29 @@ inline unsigned sweep_grid(int64_t ntasks, int32_t m)
 }
 
 template <typename T>
-hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, const SweepSlots &S,
-                    const int32_t *pend_init, double *acc, double *out, hipStream_t s)
+hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, const int32_t *slot_start,
+                    const uint8_t *slot_quad, int64_t nslots, const int32_t *pend_init, double *acc,
+                    double *out, hipStream_t s)
 {
-    if (S.n == 0) return hipGetLastError();
+    if (nslots == 0) return hipGetLastError();
     const unsigned m = (unsigned)D.m;
     k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, pend_init, nullptr, P.nb, D.ticket);
-    k_fwd_df<T><<<dim3(sweep_grid(slot_count(S), D.m), m), NT, 0, s>>>(
-        tasks, S, (int)slot_count(S), D.chunk_tptr, D.chunk_tgt, D.pend, D.ticket, D.info + 2, D.blk, D.rows,
-        (const T *)D.Lx, acc, out, P.n, P.nb, P.panel_entries);
+    k_fwd_df<T><<<dim3(sweep_grid(nslots, D.m), m), NT, 0, s>>>(
+        tasks, slot_start, slot_quad, (int)nslots, D.chunk_tptr, D.chunk_tgt, D.pend, D.ticket, D.info + 2,
+        D.blk, D.rows, (const T *)D.Lx, acc, out, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
 {
-    const SweepSlots &S = P.bwd_slots;
-    if (S.n == 0) return hipGetLastError();
+    const int64_t nslots = P.bwd_slots.count();
+    if (nslots == 0) return hipGetLastError();
     const unsigned m = (unsigned)D.m;
     k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, D.bwd_pend, D.done, P.nb, D.ticket);
-    k_bwd_df<T><<<dim3(sweep_grid(slot_count(S), D.m), m), NT, 0, s>>>(
-        D.bwd_df, S, (int)slot_count(S), D.chunk_tptr, D.chunk_tgt, D.pend, D.done, D.ticket, D.info + 2,
-        D.blk, D.rows, (const T *)D.Lx, y, P.n, P.nb, P.panel_entries);
+    k_bwd_df<T><<<dim3(sweep_grid(nslots, D.m), m), NT, 0, s>>>(
+        D.bwd_df, D.bwd_slot_start, D.bwd_slot_quad, (int)nslots, D.chunk_tptr, D.chunk_tgt, D.pend,
+        D.done, D.ticket, D.info + 2, D.blk, D.rows, (const T *)D.Lx, y, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }
 
@@ -573,9 +742,12 @@ hipError_t launch_scale(const Plan &P, const DevicePlan &D, double *y, hipStream
 
 hipError_t launch_fwd(const Plan &P, const DevicePlan &D, double *acc, double *out, hipStream_t s)
 {
+    const int64_t ns = P.fwd_slots.count();
     return prec_fp32_panels(P.precision)
-               ? fwd_impl<float>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s)
-                            : fwd_impl<double>(P, D, D.fwd_tasks, P.fwd_slots, D.fwd_pend, acc, out, s);
+               ? fwd_impl<float>(P, D, D.fwd_tasks, D.fwd_slot_start, D.fwd_slot_quad, ns, D.fwd_pend, acc,
+                                 out, s)
+               : fwd_impl<double>(P, D, D.fwd_tasks, D.fwd_slot_start, D.fwd_slot_quad, ns, D.fwd_pend, acc,
+                                  out, s);
 }
 
 hipError_t launch_bwd(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
@@ -590,8 +762,8 @@ hipError_t launch_fwd_sparse(const Plan &P, const DevicePlan &D, const DeviceRhs
     if (P.n > 0) k_zero2<<<grid_for(P.n), 256, 0, s>>>(acc, out, P.n);
     if (nbeta > 0) k_place<<<grid_for(nbeta), 256, 0, s>>>(bv, R.bpos, acc, nbeta, D.dscale);
     return prec_fp32_panels(P.precision)
-               ? fwd_impl<float>(P, D, R.tasks, R.slots, R.pend, acc, out, s)
-                            : fwd_impl<double>(P, D, R.tasks, R.slots, R.pend, acc, out, s);
+               ? fwd_impl<float>(P, D, R.tasks, R.slot_start, R.slot_quad, R.nslots, R.pend, acc, out, s)
+               : fwd_impl<double>(P, D, R.tasks, R.slot_start, R.slot_quad, R.nslots, R.pend, acc, out, s);
 }
 
 }  // namespace sym

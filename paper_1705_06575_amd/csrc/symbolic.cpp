@@ -9,6 +9,7 @@
 #include <climits>
 #include <cstring>
 #include <numeric>
+#include <stdexcept>
 
 #include "plan.hpp"
 #include "sym.h"
@@ -79,6 +80,7 @@ void build_schedule(Plan &P)
     P.parts.clear();
     P.nsplit = 0;
     P.npartial = 0;
+    P.ext_operand_entries = 0.0;
     if ((int32_t)P.svariant.size() != P.nds) P.svariant.assign((size_t)P.nds, 1);
     P.sfeat.assign((size_t)P.nds * kSuperFeatures, 0.0);
     P.sbptr.assign((size_t)P.nds + 1, 0);
@@ -117,11 +119,14 @@ void build_schedule(Plan &P)
     P.wptr.assign(1, 0);
     P.witems.clear();
     P.wmap.clear();
-    // tasks without wavefront items push their (empty) ranges here
+    P.cptr.assign(1, 0);
+    P.chunks.clear();
+    // tasks without wavefront items or chunks push their (empty) ranges here
     auto push_task = [&](int32_t J, int32_t t, int32_t K, int32_t flags, int64_t big_end) {
         P.ftasks.push_back(Task{J, t, K, flags});
         P.iptr.push_back((int64_t)P.incs.size());
         P.ibig.push_back(big_end);
+        P.cptr.push_back((int64_t)P.chunks.size());
         while ((int64_t)P.wptr.size() < 4 * (int64_t)P.ftasks.size() + 1)
             P.wptr.push_back((int64_t)P.witems.size());
     };
@@ -166,8 +171,39 @@ void build_schedule(Plan &P)
                 P.wmap.insert(P.wmap.end(), rrel.begin(), rrel.end());
                 P.wmap.insert(P.wmap.end(), crel.begin() + jlo, crel.begin() + jhi);
                 P.witems.push_back(it);
+                P.ext_operand_entries += (double)(it.nI + it.nJ) * (double)ri->wk;
             }
             P.wptr.push_back((int64_t)P.witems.size());
+        }
+    };
+    // the staged chunks of one tile's incidences (all of them, list order)
+    auto emit_chunks = [&](int32_t J, int32_t t, const std::vector<RawInc> &incs_t) {
+        for (const RawInc &ri : incs_t) {
+            relative(J, t, ri);
+            if (P.imap.size() + rrel.size() + crel.size() > (size_t)UINT32_MAX)
+                throw std::length_error("relative-index map beyond 4 GiB");
+            StageChunk c{};
+            c.valoff = P.blk[ri.K].valoff;
+            c.ld = P.blk[ri.K].ld;
+            c.b0 = ri.b0;
+            c.a0 = ri.a0;
+            c.map = (uint32_t)P.imap.size();
+            c.nI = (uint8_t)rrel.size();
+            c.nJ = (uint8_t)crel.size();
+            for (int v = 1; v < 4; ++v) {
+                int32_t j = 0;
+                while (j < (int32_t)crel.size() && crel[j] < 16 * v) ++j;
+                c.jw[v - 1] = (uint8_t)j;
+            }
+            P.imap.insert(P.imap.end(), rrel.begin(), rrel.end());
+            P.imap.insert(P.imap.end(), crel.begin(), crel.end());
+            P.ext_operand_entries += (double)(rrel.size() + crel.size()) * (double)ri.wk;
+            for (int32_t kc = 0; kc < ri.wk; kc += kStageK) {
+                const int32_t nk = std::min(kStageK, ri.wk - kc);
+                c.kc = (int16_t)kc;
+                c.nk_last = (uint8_t)(nk | (kc + kStageK >= ri.wk ? 0x80 : 0));
+                P.chunks.push_back(c);
+            }
         }
     };
     auto open_phase = [&](int32_t kind) { P.phases.push_back(Phase{kind, (int64_t)P.ftasks.size(), 0}); };
@@ -202,6 +238,7 @@ void build_schedule(Plan &P)
         in.cmin = (uint8_t)(rK[ri.a0] - dJ.col0);
         in.cmax = (uint8_t)(rK[ri.a1 - 1] - dJ.col0);
         P.incs.push_back(in);
+        P.ext_operand_entries += (double)(in.nI + in.nJ) * (double)ri.wk;
     };
     std::vector<const RawInc *> small;
     struct Pending {
@@ -306,19 +343,25 @@ void build_schedule(Plan &P)
                         if (mn >= 64) ft[5] += fl;
                         if (mn >= 32) ft[6] += fl;
                     }
+                    const bool staged = P.svariant[s2] == kVariantStaged;
                     small.clear();
-                    for (const RawInc &ri : incs_t) {
-                        if (large(ri)) emit_inc(J, t, ri);
-                        else small.push_back(&ri);
+                    if (staged) {
+                        emit_chunks(J, t, incs_t);
+                    } else {
+                        for (const RawInc &ri : incs_t) {
+                            if (large(ri)) emit_inc(J, t, ri);
+                            else small.push_back(&ri);
+                        }
                     }
                     const int64_t big_end = (int64_t)P.incs.size();
                     emit_wave_items(J, t, small);
+                    const int32_t sflag = staged ? kStaged : 0;
                     if (np > 1) {
                         P.parts.push_back(PartDesc{counter, part, np, (int32_t)slot0});
                         push_task(J, t, (int32_t)P.parts.size() - 1,
-                                  (fuse ? kFuseFactor : 0) | kPartial, big_end);
+                                  (fuse ? kFuseFactor : 0) | kPartial | sflag, big_end);
                     } else {
-                        push_task(J, t, -1, fuse ? kFuseFactor : 0, big_end);
+                        push_task(J, t, -1, (fuse ? kFuseFactor : 0) | sflag, big_end);
                     }
             }
         }
@@ -381,13 +424,15 @@ void build_schedule(Plan &P)
 }
 
 int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
-            const int32_t *user_perm, int block_width, int nd_leaf, bool relax, Plan &P)
+            const int32_t *user_perm, int block_width, int nd_leaf, bool relax, int max_width,
+            Plan &P)
 {
     auto t_start = std::chrono::steady_clock::now();
     if (n64 < 0 || n64 > INT32_MAX - 1) return SYM_EINVAL;
     if (n64 > 0 && (!Ap || !Ai)) return SYM_EINVAL;
     const int32_t n = (int32_t)n64;
     if (block_width < 16 || block_width > 64 || block_width % 16) return SYM_EINVAL;
+    if (max_width < 1 || max_width > kMaxDeviceWidth) return SYM_EINVAL;
     P.n = n;
     P.B = block_width;
 
@@ -573,7 +618,6 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
         std::vector<int32_t> top;      // fundamental supernode on top of each relaxed one
         std::vector<int32_t> first;    // first column
         std::vector<double> ztrue;     // true entries of its columns
-        std::vector<int32_t> fund2r((size_t)ns, -1);
         for (int32_t s = 0; s < ns; ++s) {
             const int32_t f = P.sptr[s], wS = P.sptr[s + 1] - f;
             const double rS = (double)(P.srowptr[s + 1] - P.srowptr[s]);
@@ -597,27 +641,55 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
                 first.push_back(f);
                 ztrue.push_back(zS);
             }
-            fund2r[s] = (int32_t)top.size() - 1;
         }
-        P.nds = (int32_t)top.size();
-        P.dsptr.assign(first.begin(), first.end());
+        // A device supernode wider than the kernels' limits is cut into
+        // pieces of consecutive columns (a piece's rows: its own columns,
+        // the later columns of the supernode, then the rows below): the
+        // update products' inner dimension is a supernode's width, held in
+        // 16 bits, and their byte offsets within a panel in 32 bits, so a
+        // piece has at most max_width columns and w * r * 8 < 2^32.  Each
+        // piece is the only child of the next; nothing else changes.
+        std::vector<int32_t> dtop, dend;
+        P.dsptr.clear();
+        for (size_t r = 0; r < top.size(); ++r) {
+            const int32_t t = top[r];
+            const int32_t f = first[r], e = P.sptr[t + 1];
+            const int64_t below = (P.srowptr[t + 1] - P.srowptr[t]) - (P.sptr[t + 1] - P.sptr[t]);
+            int32_t c = f;
+            while (c < e) {
+                const int64_t rows = (int64_t)(e - c) + below;
+                const int64_t by_bytes = (int64_t)((((uint64_t)1 << 32) - 1) / (8 * (uint64_t)rows));
+                const int32_t wmax = (int32_t)std::max<int64_t>(1, std::min<int64_t>(max_width, by_bytes));
+                P.dsptr.push_back(c);
+                dtop.push_back(t);
+                dend.push_back(e);
+                c = (int32_t)std::min<int64_t>(e, (int64_t)c + wmax);
+            }
+        }
+        P.nds = (int32_t)P.dsptr.size();
         P.dsptr.push_back(n);
         P.dsparent.assign((size_t)P.nds, -1);
         P.dsrowptr.assign((size_t)P.nds + 1, 0);
         for (int32_t r = 0; r < P.nds; ++r) {
-            const int32_t t = top[r];
-            if (P.sparent[t] >= 0) P.dsparent[r] = fund2r[P.sparent[t]];
+            const int32_t t = dtop[r];
             const int32_t wt = P.sptr[t + 1] - P.sptr[t];
             const int64_t below = (P.srowptr[t + 1] - P.srowptr[t]) - wt;
-            P.dsrowptr[r + 1] = P.dsrowptr[r] + (P.dsptr[r + 1] - P.dsptr[r]) + below;
+            P.dsrowptr[r + 1] = P.dsrowptr[r] + (dend[r] - P.dsptr[r]) + below;
         }
         P.dsrows.resize((size_t)P.dsrowptr[P.nds]);
+        std::vector<int32_t> col2ds((size_t)n);
         for (int32_t r = 0; r < P.nds; ++r) {
-            const int32_t t = top[r];
+            const int32_t t = dtop[r];
             int64_t o = P.dsrowptr[r];
-            for (int32_t j = P.dsptr[r]; j < P.dsptr[r + 1]; ++j) P.dsrows[o++] = j;
+            for (int32_t j = P.dsptr[r]; j < dend[r]; ++j) P.dsrows[o++] = j;
             const int32_t wt = P.sptr[t + 1] - P.sptr[t];
             for (int64_t p = P.srowptr[t] + wt; p < P.srowptr[t + 1]; ++p) P.dsrows[o++] = P.srows[p];
+            for (int32_t j = P.dsptr[r]; j < P.dsptr[r + 1]; ++j) col2ds[j] = r;
+        }
+        // parent: the device supernode holding the first row below the columns
+        for (int32_t r = 0; r < P.nds; ++r) {
+            const int32_t w = P.dsptr[r + 1] - P.dsptr[r];
+            if (P.dsrowptr[r + 1] - P.dsrowptr[r] > w) P.dsparent[r] = col2ds[P.dsrows[P.dsrowptr[r] + w]];
         }
     }
     P.dsvaloff.assign((size_t)P.nds + 1, 0);
@@ -897,25 +969,39 @@ SweepSlots sweep_slots(const Plan &P, const std::vector<SolveTask> &tasks, bool 
 {
     SweepSlots S;
     const int64_t n = (int64_t)tasks.size();
-    S.n = n;
-    S.t1 = 0;
-    S.t2 = n;
-    // runs of equal level: [run[i], run[i + 1])
+    // the run of wide levels: [wa, wb)
     std::vector<int64_t> run(1, 0);
     for (int64_t i = 1; i < n; ++i)
         if (P.blevel[tasks[i].J] != P.blevel[tasks[i - 1].J]) run.push_back(i);
     if (n > 0) run.push_back(n);
     const size_t nr = run.size() - 1;
+    int64_t wa = 0, wb = 0;
     if (bottom_first) {
         size_t r = 0;
         while (r < nr && run[r + 1] - run[r] >= kWideLevel) ++r;
-        S.b1 = kSlotGroup;
-        S.t1 = run[r] / kSlotGroup * kSlotGroup;
+        wa = 0;
+        wb = run[r];
     } else {
         size_t r = nr;
         while (r > 0 && run[r] - run[r - 1] >= kWideLevel) --r;
-        S.b2 = kSlotGroup;
-        S.t2 = run[r];
+        wa = run[r];
+        wb = n;
+    }
+    auto wave = [&](int64_t i) { return wave_task_block(P.blk[tasks[i].J]); };
+    int64_t i = 0;
+    S.start.push_back(0);
+    while (i < n) {
+        int64_t j = i;
+        if (wave(i)) {
+            while (j < n && j - i < 4 && wave(j)) ++j;
+            S.quad.push_back(1);
+        } else {
+            const int64_t cap = (i >= wa && i < wb) ? kSlotGroup : 1;
+            while (j < n && j - i < cap && !wave(j)) ++j;
+            S.quad.push_back(0);
+        }
+        S.start.push_back((int32_t)j);
+        i = j;
     }
     return S;
 }

@@ -86,7 +86,7 @@ def test_every_variant_factors_correctly(orc, torch_cuda):
     rng = np.random.default_rng(5)
     Ax = torch.from_numpy(w.Ax).cuda()
     for name, var in (("all 0", np.zeros(nds)), ("all 1", np.ones(nds)), ("all 2", np.full(nds, 2)),
-                      ("mixed", rng.integers(0, 3, nds))):
+                      ("all 3", np.full(nds, 3)), ("mixed", rng.integers(0, 4, nds))):
         an.set_variants(var.astype(np.uint8))
         assert np.array_equal(an.get("variant"), var.astype(np.uint8))
         an.factor(Ax)

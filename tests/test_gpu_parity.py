@@ -126,6 +126,57 @@ def test_amalgamation_modes(S, orc, torch_cuda, amalgamate):
         assert res <= 1e-13 and eL <= 1e-10
 
 
+@pytest.mark.parametrize("max_width", [7, 40])
+def test_cut_supernodes(S, orc, torch_cuda, max_width):
+    """Device supernodes cut into pieces of at most max_width columns (the
+    rule that keeps the kernels' 16-bit widths and 32-bit panel offsets in
+    range, forced here at small widths): factor and solve against the
+    oracle as for the uncut plan."""
+    torch = torch_cuda
+    for w in [W.random_spd(200, 1.0, np.random.default_rng(6)), W.config2(14)]:
+        _say(f"case {w.name} max_super_width={max_width}")
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, max_super_width=max_width)
+        an.factor(torch.from_numpy(w.Ax).cuda())
+        assert an.status() == 0
+        f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+        Lx = an.export_factor()
+        eL = _rel(Lx, f["Lx"])
+        res = orc.llt_residual(w.n, f["Cp"], f["Ci"], f["Cx"], f["Lp"], f["Li"], Lx)
+        b = W.dense_rhs(w.n, np.random.default_rng(12))
+        x = an.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+        xr = orc.solve(w.n, w.perm, f["Lp"], f["Li"], f["Lx"], b)
+        ex = _rel(x, xr)
+        _say(f"  factor rel diff {eL:.3e} llt residual {res:.3e} solve rel diff {ex:.3e}")
+        assert res <= 1e-13 and eL <= 1e-10 and ex <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+def test_staged_external_updates(S, orc, torch_cuda, precision):
+    """Every device supernode on the staged external-update path (variant
+    3: each incidence's rows staged in LDS once per tile, in chunks of 16
+    inner indices): the factor against the oracle as for the default
+    variant, in FP64, FP32 and with bfloat16 update products."""
+    torch = torch_cuda
+    tol = {"f64": 1e-13, "f32": 1e-5, "bf16": None}[precision]
+    for w in [W.random_spd(200, 1.0, np.random.default_rng(6)), W.config2(14),
+              W.knn_instance(3, nv=900)]:
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision=precision)
+        an.set_variants(np.full(int(an.stat("ndsuper")), 3, np.uint8))
+        an.factor(torch.from_numpy(w.Ax).cuda())
+        assert an.status() == 0
+        f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+        Lx = an.export_factor()
+        eL = _rel(Lx, f["Lx"])
+        res = orc.llt_residual(w.n, f["Cp"], f["Ci"], f["Cx"], f["Lp"], f["Li"], Lx)
+        _say(f"case staged {precision} {w.name}: factor rel diff {eL:.3e} llt residual {res:.3e}")
+        if tol is None:
+            assert res <= 4.0 * 2.0 ** -8
+        else:
+            assert res <= (1e-13 if precision == "f64" else 1e-5)
+            if not w.name.startswith("grid3d"):
+                assert eL <= tol
+
+
 def test_dense_multi_block_multi_tile(S, orc, torch_cuda):
     """Fully dense 200 x 200: one supernode cut into 4 blocks of <= 64
     columns with up to 4 row tiles each (exercises the off-diagonal tile
@@ -163,6 +214,16 @@ def test_config1_full(S, orc, torch_cuda):
         _say(f"  sparse rhs nb={nb} reach={ref_reach.size} rel diff {e:.3e}")
         assert e <= tol_x
         assert _rel(orc.lmul(w.n, f["Lp"], f["Li"], Lx, y), b) <= 1e-13
+        # the full solve with the same sparse right-hand side (pruned forward
+        # sweep, full backward sweep), original ordering, against the
+        # oracle's dense solve of that b
+        bo = np.zeros(w.n)
+        bo[pos] = val
+        x = an.solve_sparse(r, torch.from_numpy(val).cuda()).cpu().numpy()
+        x_ref = orc.solve(w.n, w.perm, f["Lp"], f["Li"], f["Lx"], bo)
+        ex = _rel(x, x_ref)
+        _say(f"  full solve, sparse rhs nb={nb}: rel diff {ex:.3e}")
+        assert ex <= tol_x
 
 
 def test_indefinite_reports_first_pivot(S, orc, torch_cuda):

@@ -277,3 +277,22 @@ def test_symbolic_matches_oracle_full_size(S, orc, cfg):
         n, Ap, Ai, _, perm = W.config4_batch(cfg.split("_")[1], 1)
         w = _Pat(cfg, n, Ap, Ai, perm)
     _check_symbolic(S, orc, w, perm)
+
+
+def test_wide_supernodes_are_cut_into_pieces(S, orc):
+    """Device supernodes wider than max_super_width are cut into pieces of
+    consecutive columns: the reported (fundamental) structure is unchanged,
+    every device block stays within one piece's width limit, and the
+    schedule still covers the method's arithmetic exactly."""
+    w = W.config2(16)
+    base = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm)
+    assert max(np.diff(base.get("blocks"))) == 64
+    for mw in (1, 7, 40):
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, max_super_width=mw)
+        for k in ("parent", "colcount", "Lp", "Li", "super"):
+            assert np.array_equal(an.get(k), base.get(k))
+        assert an.stat("ndsuper") > base.stat("ndsuper")
+        assert max(np.diff(an.get("blocks"))) <= mw
+        assert sum(an.kind_flops().values()) == an.stat("flops")
+    with pytest.raises(Exception):
+        S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, max_super_width=16385)
