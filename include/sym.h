@@ -90,7 +90,11 @@ typedef struct sym_opts {
                                 ones whose w x r panel reaches 4 GiB, are cut into pieces of
                                 consecutive columns (device panels only; the reported
                                 supernodes stay the fundamental ones) */
-    int32_t reserved[5];
+    int32_t split_share;     /* an external-update tile costing more than max(64, level cost /
+                                split_share) units (16-wide inner batches) is cut into parts of
+                                about that size, run by separate workgroups (0 = 12288;
+                                1..2^24) */
+    int32_t reserved[4];
 } sym_opts;
 
 typedef struct sym_plan *sym_handle;

@@ -51,7 +51,8 @@ class sym_opts(ctypes.Structure):
                 ("amalgamate", ctypes.c_int32),
                 ("pivot_floor_exp", ctypes.c_int32),
                 ("max_super_width", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("split_share", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
@@ -180,7 +181,7 @@ class Analysis:
     """
 
     def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=24,
-                 amalgamate=True, pivot_floor_exp=0, max_super_width=0):
+                 amalgamate=True, pivot_floor_exp=0, max_super_width=0, split_share=0):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -203,6 +204,7 @@ class Analysis:
         o.precision = PRECISIONS[precision]
         o.pivot_floor_exp = int(pivot_floor_exp)
         o.max_super_width = int(max_super_width)
+        o.split_share = int(split_share)
         o.nd_leaf = int(nd_leaf)
         o.amalgamate = int(bool(amalgamate))
         self.precision = precision

@@ -178,11 +178,13 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
     if (opts) o = *opts;
     if (o.precision < SYM_F64 || o.precision > SYM_F16) return SYM_EINVAL;
     if (o.pivot_floor_exp < -60 || o.pivot_floor_exp > 1) return SYM_EINVAL;
+    if (o.split_share < 0 || o.split_share > (1 << 24)) return SYM_EINVAL;
     sym_plan *h = new (std::nothrow) sym_plan();
     if (!h) return SYM_ENOMEM;
     int rc;
     try {
         h->P.precision = o.precision;
+        if (o.split_share > 0) h->P.split_share = o.split_share;
         // pivot floor of the scaled precisions: 2^exp, the default by format
         // (SYM_PIVOT_FLOOR_DEFAULT_*), or none (exp = 1)
         if (sym::prec_scaled(o.precision) && o.pivot_floor_exp != 1) {

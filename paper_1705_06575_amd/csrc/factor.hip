@@ -443,7 +443,7 @@ __device__ __forceinline__ float pivot_rsqrt(float d)
 // pivot below its column's floor is replaced by the floor (the factor is
 // then that of a matrix with a slightly larger diagonal; the count of
 // replacements goes to info[3]); a NaN pivot is never replaced.
-template <typename T>
+template <typename T, bool FLOOR>
 __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
                                               int32_t *info, const double *floor)
 {
@@ -454,12 +454,12 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
     double r[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) r[c] = (mine && c < wb) ? (double)C[(c0 + c) * LDC + row] : 0.0;
-    const double fl = floor ? floor[c0 + min(lane & 15, wb - 1)] : 0.0;
+    const double fl = (FLOOR && floor) ? floor[c0 + min(lane & 15, wb - 1)] : 0.0;
     int bad = INT_MAX, nrep = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         double d = lane_value(r[k], k);
-        if (floor) {
+        if (FLOOR && floor) {
             const double f = lane_value(fl, k);
             if (k < wb && d < f) {
                 if (lane == k) r[k] = f;
@@ -480,7 +480,7 @@ __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int 
         }
     }
     if (bad != INT_MAX && lane == 0) atomicMin(info, bad);
-    if (nrep && lane == 0) atomicAdd(info + 3, nrep);
+    if (FLOOR && nrep && lane == 0) atomicAdd(info + 3, nrep);
 #pragma unroll
     for (int c = 0; c < 16; ++c)
         if (mine && c < wb) C[(c0 + c) * LDC + row] = (T)r[c];
@@ -608,20 +608,21 @@ __device__ __forceinline__ void block_update(T *C, const T *X, const T *Y, int r
 // beyond it (matrix-core products).  Every column still receives the
 // sub-panels' updates in order.  Called by all threads of the workgroup.
 // Every factorization of a diagonal block runs here in FP64 (FP32 panels
-// are widened into an FP64 tile first and rounded once when stored).
-template <typename T>
+// are widened into an FP64 tile first and rounded once when stored).  The
+// pivot floor exists only where FLOOR is set (the 16-bit update precisions).
+template <bool FLOOR, typename T>
 __device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info,
                                              const double *floor)
 {
     const int wave = threadIdx.x >> 6;
-    if (wave == 0) wave_subpanel(C, 0, min(16, w), nr, col0, info, floor);
+    if (wave == 0) wave_subpanel<T, FLOOR>(C, 0, min(16, w), nr, col0, info, floor);
     __syncthreads();
     for (int c0 = 16; c0 < w; c0 += 16) {
         const int wb = min(16, w - c0);
         block_update(C, C, C, c0, nr, c0, c0 + wb, c0 - 16, 16, 0);
         __syncthreads();
         if (wave == 0)
-            wave_subpanel(C, c0, wb, nr, col0, info, floor);
+            wave_subpanel<T, FLOOR>(C, c0, wb, nr, col0, info, floor);
         else if (c0 + wb < w)
             block_update(C, C, C, c0 + wb, nr, c0 + wb, w, c0 - 16, 16, 0, 1);
         __syncthreads();
@@ -1323,7 +1324,7 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     if (finish) {
         if (tk.flags & kFuseFactor) {
             widen_tile<T>(Cbuf);
-            panel_factor(Cbuf, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
+            panel_factor<OP != kOpNative>(Cbuf, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
             tile_out(LJ + r0, Cbuf, J.ld, nr, w);
         } else {
             tile_out(LJ + r0, C, J.ld, nr, w);
@@ -1401,7 +1402,7 @@ __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tas
                     }
         }
         __syncthreads();
-        panel_factor(C, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
+        panel_factor<OP != kOpNative>(C, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
         tile_out(LJ + r0, C, J.ld, nr, w);
     } else if (active) {
 #pragma unroll

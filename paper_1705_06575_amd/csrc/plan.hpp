@@ -187,6 +187,7 @@ struct Plan {
     int64_t nnzA = 0;
     int32_t B = 64;             // block width
     int32_t precision = 0;      // kPrec*
+    double split_share = kSplitShare;  // a long external tile's part: max(kSplitUnits, level cost / share)
     double pivot_floor = 0.0;   // tau: pivots below tau times their scaled diagonal entry are
                                 // replaced by it (scaled precisions only; 0 = never)
     double analyze_ms = 0.0;

@@ -302,7 +302,7 @@ void build_schedule(Plan &P)
         int64_t lv_slots = 0;
         double lv_cost = 0.0;
         for (const Pending &pd : pending) lv_cost += pd.cost;
-        const double unit = std::max(kSplitUnits, lv_cost / kSplitShare);
+        const double unit = std::max(kSplitUnits, lv_cost / P.split_share);
         for (const Pending &pd : pending) {
             int32_t np = 1;
             if (pd.cost > unit)

@@ -29,10 +29,17 @@ def test_autotune_picks_fastest_and_is_correct(orc, torch_cuda):
     print("case autotune:", [(t["block_width"], t["amalgamate"], round(t["ms"], 3)) for t in table],
           "best", best, flush=True)
     sys.stdout.flush()
-    assert len(table) == len(autotune.SPACE)
+    assert len(table) == len(autotune.SPACE) + len(autotune.SHARES)
     assert all(t["ok"] for t in table)
     fastest = min(table, key=lambda t: t["ms"])
-    assert best == {"block_width": fastest["block_width"], "amalgamate": fastest["amalgamate"]}
+    want = {"block_width": fastest["block_width"], "amalgamate": fastest["amalgamate"]}
+    if fastest.get("split_share"):
+        want["split_share"] = fastest["split_share"]
+    assert best == want
+    # the second stage varied only the split share, around the first stage's winner
+    first = min(table[:len(autotune.SPACE)], key=lambda t: t["ms"])
+    for t in table[len(autotune.SPACE):]:
+        assert (t["block_width"], t["amalgamate"]) == (first["block_width"], first["amalgamate"])
     # every candidate has the same method flop count (amalgamation adds stored zeros only)
     assert len({t["flops"] for t in table}) == 1
     an = S.Analysis(n, Ap, Ai, ordering=perm, precision="f64", **best)

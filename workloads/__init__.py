@@ -304,6 +304,44 @@ def config4_batch(kind: str, m: int, k0: int = 0):
     return n, Ap, Ai, X, grid_nd_order(shape)
 
 
+def block_diagonal(parts):
+    """The block-diagonal union of patterns: parts = [(n_i, Ap_i, Ai_i,
+    X_i, perm_i), ...] with X_i an (m, nnz_i) value array (the same m for
+    every part).  Returns (n, Ap, Ai, X, perm, offsets): the union's lower
+    CSC, its (m, nnz) values (each row the parts' rows side by side), the
+    parts' orderings placed one after another, and each part's first
+    unknown (offsets[-1] = n)."""
+    m = parts[0][3].shape[0]
+    offsets = np.cumsum([0] + [p[0] for p in parts])
+    Ap = [np.zeros(1, np.int64)]
+    Ai, X, perm = [], [], []
+    nnz = 0
+    for (n_i, Ap_i, Ai_i, X_i, perm_i), off in zip(parts, offsets[:-1]):
+        assert X_i.shape[0] == m
+        Ap.append(Ap_i[1:] + nnz)
+        Ai.append(Ai_i.astype(np.int64) + off)
+        X.append(X_i)
+        perm.append(np.asarray(perm_i, np.int64) + off)
+        nnz += int(Ap_i[-1])
+    return (int(offsets[-1]), np.concatenate(Ap), np.concatenate(Ai).astype(np.int32),
+            np.concatenate(X, axis=1), np.concatenate(perm).astype(np.int32), offsets)
+
+
+def config4_union(m: int = 64, copies_9pt: int = 8):
+    """The batched workload as one pattern with m value sets: the
+    block-diagonal union of copies_9pt 2-D 9-point 128^2 grids, one 3-D
+    7-point 24^3 and one 40^3 grid.  Value set i holds instances
+    copies_9pt * i .. copies_9pt * i + copies_9pt - 1 of the 9-point family
+    and instance i of each 3-D family (the same values as config4_batch),
+    so m = 64 value sets carry 512 + 64 + 64 instances.  Returns
+    block_diagonal's tuple."""
+    n9, Ap9, Ai9, X9, p9 = config4_batch("9pt128", copies_9pt * m)
+    parts = [(n9, Ap9, Ai9, X9[c::copies_9pt], p9) for c in range(copies_9pt)]
+    for kind in ("7pt24", "7pt40"):
+        parts.append(config4_batch(kind, m))
+    return block_diagonal(parts)
+
+
 def random_spd_3x3(rng, count):
     """count random SPD 3x3 blocks Q diag(lambda) Q^T, Q Haar, lambda ~ U[0.1, 10]."""
     g = rng.standard_normal((count, 3, 3))
