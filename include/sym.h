@@ -94,7 +94,13 @@ typedef struct sym_opts {
                                 split_share) units (16-wide inner batches) is cut into parts of
                                 about that size, run by separate workgroups (0 = 12288;
                                 1..2^24) */
-    int32_t reserved[4];
+    int32_t chain_launch;    /* 0 (default): the steps inside the supernodes of a level (off-diagonal
+                                solves of their first blocks, then for every later block its update
+                                by the previous one, its factorization and its solves) run as one
+                                launch per step and kind; 1: as one persistent launch per level
+                                whose tasks wait for the tiles they read (same results, bit for
+                                bit; measured slower on this chip, kept for comparison) */
+    int32_t reserved[3];
 } sym_opts;
 
 typedef struct sym_plan *sym_handle;
@@ -276,7 +282,7 @@ int sym_export_factor(sym_handle h, double *Lx_host, void *stream);
 #define SYM_GET_SPARENT 7     /* int32[ns]  supernodal elimination tree */
 #define SYM_GET_BLOCKS 8      /* int32[nb+1] first column of each device block, then n */
 #define SYM_GET_BLEVEL 9      /* int32[nb]  level of each block (leaves 0) */
-#define SYM_GET_SUPER_FEAT 10 /* double[nds*8] features of each device supernode (see below) */
+#define SYM_GET_SUPER_FEAT 10 /* double[nds*12] features of each device supernode (see below) */
 #define SYM_GET_TASK_SUPER 11 /* int32[ntasks] device supernode an external-update task
                                  updates, -1 for the factor's other tasks */
 #define SYM_GET_VARIANT 12    /* uint8[nds] kernel variant of each device supernode */
@@ -327,18 +333,23 @@ int sym_profile_read(sym_handle h, double *ms, int64_t *launches, double *algori
  * Per-supernode kernel variants (the choices a cost model makes).  The
  * external update of device supernode s (nds = SYM_STAT_NDSUPER of them)
  * runs its incidences -- (row tile, descendant) products -- either all as
- * per-wavefront items (variant 0) or, for those with at least 64 (variant
+ * per-wavefront items (variant 0), or, for those with at least 64 (variant
  * 1, the default) or 32 (variant 2) rows, columns and inner indices, on
- * the whole workgroup through LDS.  Results do not depend on the variant
- * beyond rounding order.  SYM_GET_SUPER_FEAT gives 8 features per device
- * supernode: width, rows, row tiles receiving updates, incidences
+ * the whole workgroup through LDS, or all as staged chunks whose rows are
+ * read once per tile into LDS (variant 3).  Results do not depend on the
+ * variant beyond rounding order.  SYM_GET_SUPER_FEAT gives 12 features per
+ * device supernode: width, rows, row tiles receiving updates, incidences
  * received, their product flops, the fractions of those flops in
- * incidences of >= 64 and >= 32 rows, columns and inner indices, level.
+ * incidences of >= 64 and >= 32 rows, columns and inner indices, level;
+ * then the context of its level (the supernodes whose updates share its
+ * launches): the level's update flops, its number of supernodes, its row
+ * tiles receiving updates, and this supernode's share of the level's
+ * update flops.
  *
- * sym_set_variants: variant[nds] (values 0..2) for every device supernode;
+ * sym_set_variants: variant[nds] (values 0..3) for every device supernode;
  * rebuilds the schedule on the host, so the workspace size may change and
  * the handle must be bound again (it is left unbound).  Errors:
- * SYM_EINVAL (count != nds or a value > 2).
+ * SYM_EINVAL (count != nds or a value > 3).
  *
  * sym_task_times: for the most recent sym_factor run with profiling
  * enabled (sym_profile), the duration in microseconds of every factor
@@ -360,14 +371,18 @@ int sym_task_times(sym_handle h, double *us);
  * sym_mlp_forward: y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 per sample.
  * sym_mlp_backward: grad_dev = the gradient, with respect to every
  * parameter, of the mean squared error (1/n) sum (y - t)^2; work_dev:
- * caller scratch of n * (4 * 64 + 1) floats.  Each gradient entry is a sum
- * over samples in sample order (bitwise reproducible).
+ * caller scratch of sym_mlp_work_size(n, d_in) floats.  Each gradient
+ * entry is a sum over samples in a fixed order -- 64 chunks of consecutive
+ * samples, each summed in sample order, then the chunk sums in chunk order
+ * -- so gradients are bitwise reproducible.
+ * sym_mlp_work_size: *floats = n * (4 * 64 + 1) + 64 * param_count.
  * sym_mlp_adam: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step
  * counted from 1) on params_dev with moment buffers m_dev, v_dev.
  * All run on `stream` without synchronizing.  Errors: SYM_EINVAL, SYM_EHIP.
  */
 #define SYM_MLP_HIDDEN 64
 int sym_mlp_param_count(int32_t d_in, int64_t *count);
+int sym_mlp_work_size(int32_t n, int32_t d_in, int64_t *floats);
 int sym_mlp_forward(const float *params_dev, const float *X_dev, int32_t n, int32_t d_in,
                     float *y_dev, void *stream);
 int sym_mlp_backward(const float *params_dev, const float *X_dev, const float *t_dev, int32_t n,

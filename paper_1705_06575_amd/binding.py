@@ -52,7 +52,8 @@ class sym_opts(ctypes.Structure):
                 ("pivot_floor_exp", ctypes.c_int32),
                 ("max_super_width", ctypes.c_int32),
                 ("split_share", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("chain_launch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
@@ -62,7 +63,7 @@ EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_
            "sym_profile", "sym_profile_read", "sym_refine", "sym_refine_pcg", "sym_destroy",
            "sym_rhs_destroy", "sym_batch_create", "sym_batch_workspace", "sym_batch_bind",
            "sym_batch_factor", "sym_batch_solve", "sym_batch_refine", "sym_batch_eta",
-           "sym_batch_status", "sym_batch_destroy", "sym_set_variants", "sym_task_times", "sym_mlp_param_count", "sym_mlp_forward",
+           "sym_batch_status", "sym_batch_destroy", "sym_set_variants", "sym_task_times", "sym_mlp_param_count", "sym_mlp_work_size", "sym_mlp_forward",
            "sym_mlp_backward", "sym_mlp_adam"]
 
 _lib = None
@@ -122,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     L.sym_batch_eta.argtypes = [vp, vp, vp, vp, vp, vp]
     L.sym_batch_status.argtypes = [vp, vp]
     L.sym_mlp_param_count.argtypes = [ctypes.c_int32, ctypes.POINTER(i64)]
+    L.sym_mlp_work_size.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(i64)]
     L.sym_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
     L.sym_mlp_backward.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.sym_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_float, vp]
@@ -141,6 +143,14 @@ def load_library(path: str = LIB_PATH):
 def _check(call, rc):
     if rc != 0:
         raise SymError(call, rc)
+
+
+def mlp_work_size(n: int, d_in: int) -> int:
+    """Floats of scratch sym_mlp_backward needs for n samples of d_in inputs."""
+    L = load_library()
+    out = ctypes.c_int64()
+    _check("sym_mlp_work_size", L.sym_mlp_work_size(int(n), int(d_in), ctypes.byref(out)))
+    return out.value
 
 
 def opts_default() -> sym_opts:
@@ -181,7 +191,8 @@ class Analysis:
     """
 
     def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=24,
-                 amalgamate=True, pivot_floor_exp=0, max_super_width=0, split_share=0):
+                 amalgamate=True, pivot_floor_exp=0, max_super_width=0, split_share=0,
+                 chain_launch=False):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -205,6 +216,7 @@ class Analysis:
         o.pivot_floor_exp = int(pivot_floor_exp)
         o.max_super_width = int(max_super_width)
         o.split_share = int(split_share)
+        o.chain_launch = int(bool(chain_launch))
         o.nd_leaf = int(nd_leaf)
         o.amalgamate = int(bool(amalgamate))
         self.precision = precision

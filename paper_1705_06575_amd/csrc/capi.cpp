@@ -25,7 +25,8 @@ struct sym_plan {
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
            off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
-           off_parts = 0, off_pcount = 0, off_pbuf = 0, off_invb = 0,
+           off_parts = 0, off_pcount = 0, off_pbuf = 0, off_invb = 0, off_tbase = 0, off_tinit = 0,
+           off_tstate = 0, off_ctk = 0,
            off_info = 0, off_dscale = 0, off_pfloor = 0, off_adiag = 0, off_acoord = 0,
            off_dsptr = 0, off_fss = 0, off_fsq = 0, off_bss = 0, off_bsq = 0, off_cptr = 0,
            off_chunks = 0;
@@ -123,6 +124,10 @@ void layout(sym_plan *h)
     h->off_fsq = take(P.fwd_slots.quad.size());
     h->off_bss = take(sizeof(int32_t) * P.bwd_slots.start.size());
     h->off_bsq = take(P.bwd_slots.quad.size());
+    h->off_tbase = take(sizeof(int32_t) * P.tbase.size());
+    h->off_tinit = take(sizeof(int32_t) * P.tinit.size());
+    h->off_tstate = take(sizeof(int32_t) * P.tinit.size());
+    h->off_ctk = take(sizeof(int32_t) * (size_t)P.nchain);
     h->ws_bytes = o;
 }
 
@@ -179,12 +184,14 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
     if (o.precision < SYM_F64 || o.precision > SYM_F16) return SYM_EINVAL;
     if (o.pivot_floor_exp < -60 || o.pivot_floor_exp > 1) return SYM_EINVAL;
     if (o.split_share < 0 || o.split_share > (1 << 24)) return SYM_EINVAL;
+    if (o.chain_launch != 0 && o.chain_launch != 1) return SYM_EINVAL;
     sym_plan *h = new (std::nothrow) sym_plan();
     if (!h) return SYM_ENOMEM;
     int rc;
     try {
         h->P.precision = o.precision;
         if (o.split_share > 0) h->P.split_share = o.split_share;
+        h->P.chain_launch = o.chain_launch != 0;
         // pivot floor of the scaled precisions: 2^exp, the default by format
         // (SYM_PIVOT_FLOOR_DEFAULT_*), or none (exp = 1)
         if (sym::prec_scaled(o.precision) && o.pivot_floor_exp != 1) {
@@ -201,6 +208,8 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
         rc = SYM_ENOMEM;
     } catch (const std::length_error &) {
         rc = SYM_ENOMEM;
+    } catch (const std::logic_error &) {           // a schedule that failed its own check
+        rc = SYM_ESCHED;
     }
     if (rc != SYM_OK) {
         delete h;
@@ -272,6 +281,10 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.fwd_slot_quad = (uint8_t *)(base + h->off_fsq);
     D.bwd_slot_start = (int32_t *)(base + h->off_bss);
     D.bwd_slot_quad = (uint8_t *)(base + h->off_bsq);
+    D.tbase = (int32_t *)(base + h->off_tbase);
+    D.tinit = (int32_t *)(base + h->off_tinit);
+    D.tstate = (int32_t *)(base + h->off_tstate);
+    D.cticket = (int32_t *)(base + h->off_ctk);
     const bool sc = sym::prec_scaled(P.precision);
     D.dscale = sc ? (double *)(base + h->off_dscale) : nullptr;
     D.pfloor = sc ? (double *)(base + h->off_pfloor) : nullptr;
@@ -287,6 +300,8 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess)
         e = upload(D.bwd_slot_start, P.bwd_slots.start.data(), sizeof(int32_t) * P.bwd_slots.start.size(), s);
     if (e == hipSuccess) e = upload(D.bwd_slot_quad, P.bwd_slots.quad.data(), P.bwd_slots.quad.size(), s);
+    if (e == hipSuccess) e = upload(D.tbase, P.tbase.data(), sizeof(int32_t) * P.tbase.size(), s);
+    if (e == hipSuccess) e = upload(D.tinit, P.tinit.data(), sizeof(int32_t) * P.tinit.size(), s);
     if (sc && e == hipSuccess) {
         e = upload(D.adiag, P.adiag.data(), sizeof(int64_t) * P.adiag.size(), s);
         if (e == hipSuccess) e = upload(D.acoord, P.acoord.data(), sizeof(int32_t) * P.acoord.size(), s);
@@ -465,6 +480,8 @@ int sym_set_variants(sym_handle h, const uint8_t *variant, int32_t count)
         return SYM_ENOMEM;
     } catch (const std::length_error &) {
         return SYM_ENOMEM;
+    } catch (const std::logic_error &) {
+        return SYM_ESCHED;
     }
     layout(h);
     h->bound = false;
@@ -911,6 +928,13 @@ int sym_mlp_param_count(int32_t d_in, int64_t *count)
     return SYM_OK;
 }
 
+int sym_mlp_work_size(int32_t n, int32_t d_in, int64_t *floats)
+{
+    if (!floats || n < 0 || d_in < 1 || d_in > sym::kMlpMaxIn) return SYM_EINVAL;
+    *floats = sym::mlp_work_floats(n, d_in);
+    return SYM_OK;
+}
+
 int sym_mlp_forward(const float *params_dev, const float *X_dev, int32_t n, int32_t d_in,
                     float *y_dev, void *stream)
 {
@@ -945,7 +969,8 @@ struct sym_batch {
     sym_plan *h = nullptr;
     int32_t m = 0;
     size_t ws_bytes = 0, off_Lx = 0, off_vec = 0, off_vec2 = 0, off_vec3 = 0, off_info = 0,
-           off_red = 0, off_sync = 0, off_pcount = 0, off_pbuf = 0, off_dscale = 0, off_pfloor = 0;
+           off_red = 0, off_sync = 0, off_pcount = 0, off_pbuf = 0, off_dscale = 0, off_pfloor = 0,
+           off_tstate = 0, off_ctk = 0;
     sym::DevicePlan D;              // the analysis's plan arrays, the batch's own buffers
     bool bound = false, factored = false;
     uint64_t generation = 0;        // the analysis's generation when the batch was bound
@@ -984,6 +1009,8 @@ int sym_batch_create(sym_handle h, int32_t m, sym_batch_t *out)
     const bool sc = sym::prec_scaled(P.precision);
     b->off_dscale = take(sc ? M * sizeof(double) * (size_t)P.n : 0);
     b->off_pfloor = take(sc ? M * sizeof(double) * (size_t)P.n : 0);
+    b->off_tstate = take(M * sizeof(int32_t) * P.tinit.size());
+    b->off_ctk = take(M * sizeof(int32_t) * (size_t)P.nchain);
     b->ws_bytes = std::max<size_t>(o, 256);
     *out = b;
     return SYM_OK;
@@ -1020,6 +1047,8 @@ int sym_batch_bind(sym_batch_t b, void *dev_ws, size_t bytes, void *stream)
         D.dscale = (double *)(base + b->off_dscale);
         D.pfloor = (double *)(base + b->off_pfloor);
     }
+    D.tstate = (int32_t *)(base + b->off_tstate);
+    D.cticket = (int32_t *)(base + b->off_ctk);
     // single-instance scratch of the analysis is not used by batches
     D.vec4 = D.vec5 = D.vec6 = D.part = nullptr;
     D.ttime = nullptr;

@@ -72,6 +72,11 @@ struct DevicePlan {
     int64_t *adiag = nullptr;       // n
     int32_t *acoord = nullptr;      // 2 nnzA
     int32_t *dsptr = nullptr;       // nds + 1
+    // chain launches
+    int32_t *tbase = nullptr;       // nb + 1: first tile of each block
+    int32_t *tinit = nullptr;       // tiles: initial tile states
+    int32_t *tstate = nullptr;      // tiles (per instance): live tile states
+    int32_t *cticket = nullptr;     // nchain (per instance): next task of each chain launch
 };
 
 // Reach-pruned forward sweep schedule, device view.
@@ -147,10 +152,12 @@ hipError_t launch_xpby(const Plan &P, double *p, const double *z, double b, hipS
 // ---- cost-model network (mlp.hip)
 constexpr int kMlpHidden = 64;      // units per hidden layer
 constexpr int kMlpMaxIn = 32;       // input features at most
+constexpr int kMlpGradChunks = 64;  // sample chunks of the gradient reduction
 int64_t mlp_param_count(int D);
+int64_t mlp_work_floats(int n, int D);   // backward scratch: per-sample values + chunk sums
 hipError_t launch_mlp_forward(const float *params, const float *X, int n, int D, float *y,
                               hipStream_t s);
-// grad = gradient of the mean squared error; work: n * (4 * kMlpHidden + 1) floats
+// grad = gradient of the mean squared error; work: mlp_work_floats(n, D) floats
 hipError_t launch_mlp_backward(const float *params, const float *X, const float *t, int n, int D,
                                float *grad, float *work, hipStream_t s);
 hipError_t launch_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,

@@ -54,6 +54,36 @@ constexpr int NT = 256;           // threads per workgroup (4 wavefronts)
 constexpr int TR = kTileRows;     // tile rows (64)
 constexpr int LDC = TR + 1;       // LDS column stride of a tile
 
+// Loads and stores of panel values that another workgroup of the same
+// launch writes or reads take the device-coherence bit (sc1): the form of a
+// device-scope relaxed atomic access, coherent across the chip's per-die L2
+// caches.  They go through a raw buffer resource over the 4 GiB from a base
+// address (a device panel never reaches 4 GiB), so the address is a scalar
+// base plus a 32-bit byte offset, as for the plain loads.
+constexpr int kCoherentBit = 16;        // the cache-policy operand's sc1 bit
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t coherent_rsrc(const void *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, -1, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T coherent_ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kCoherentBit));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kCoherentBit));
+}
+template <typename T>
+__device__ __forceinline__ void coherent_st(__amdgpu_buffer_rsrc_t r, uint32_t off, T v)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
+                                              r, off, 0, kCoherentBit);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, kCoherentBit);
+}
+
 // Copy the nr x w column-major block at src (leading dimension ld; nr, w
 // <= 64) into LDS (stride LDC) with all threads.  Thread t moves row t % 64
 // of columns t / 64 + 4u: every load is issued before the first store, so
@@ -325,7 +355,7 @@ template <typename T>
 struct Chunk16 {
     T a0[4], a1[4], b0[4], b1[4];
 };
-template <typename T, int OP>
+template <typename T, int OP, bool COH = false>
 __device__ __forceinline__ void wave_product_pipe(const T *__restrict__ pa, const T *__restrict__ pb,
                                                   int64_t ld, int nI, int nJ, int wk, int wr, int wc,
                                                   typename Mfma<T>::acc_t (&acc)[2][2])
@@ -339,14 +369,22 @@ __device__ __forceinline__ void wave_product_pipe(const T *__restrict__ pa, cons
     const uint32_t ldb = sizeof(T) * (uint32_t)ld;
     const char *ca = reinterpret_cast<const char *>(pa);
     const char *cbp = reinterpret_cast<const char *>(pb);
+    const __amdgpu_buffer_rsrc_t rsa = coherent_rsrc(pa), rsb = coherent_rsrc(pb);
     auto load = [&](Chunk16<T> &x, int kc) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             const uint32_t ko = (uint32_t)min(kc + 4 * st + lk, wk - 1) * ldb;
-            x.a0[st] = *reinterpret_cast<const T *>(ca + (ra0 + ko));
-            x.a1[st] = *reinterpret_cast<const T *>(ca + (ra1 + ko));
-            x.b0[st] = *reinterpret_cast<const T *>(cbp + (cb0 + ko));
-            x.b1[st] = *reinterpret_cast<const T *>(cbp + (cb1 + ko));
+            if constexpr (COH) {
+                x.a0[st] = coherent_ld<T>(rsa, ra0 + ko);
+                x.a1[st] = coherent_ld<T>(rsa, ra1 + ko);
+                x.b0[st] = coherent_ld<T>(rsb, cb0 + ko);
+                x.b1[st] = coherent_ld<T>(rsb, cb1 + ko);
+            } else {
+                x.a0[st] = *reinterpret_cast<const T *>(ca + (ra0 + ko));
+                x.a1[st] = *reinterpret_cast<const T *>(ca + (ra1 + ko));
+                x.b0[st] = *reinterpret_cast<const T *>(cbp + (cb0 + ko));
+                x.b1[st] = *reinterpret_cast<const T *>(cbp + (cb1 + ko));
+            }
         }
     };
     auto compute = [&](const Chunk16<T> &x, int kc) {
@@ -1450,6 +1488,226 @@ __global__ __launch_bounds__(NT) void k_trsm(const Task *__restrict__ tasks,
     tile_out(LJ + r0, X, J.ld, nr, w);
 }
 
+// ------------------------------------------------------------ chain launch
+//
+// The steps inside the supernodes of one level (off-diagonal solves of the
+// first blocks, then for every later block: the update by the previous
+// block, the factorization of its diagonal tile and the solves of its other
+// tiles) as one persistent launch.  Workgroups take tasks in the analysis's
+// order (every task after the tasks it waits for) from a device counter,
+// and a task waits for the tile states it needs: its own tile's previous
+// update and the final tiles of the source block it reads (tile states as
+// in Plan::tbase).  Values handed between the tasks of the launch are
+// loaded and stored with device-coherent accesses; a task's state is
+// published only after all of its stores have completed.  So the next
+// block's factorization starts as soon as the tiles it reads are final,
+// while the rest of the previous step's updates still run.
+
+constexpr int kChainSpin = 1 << 22;     // sleeps of ~0.2 us: about a second
+constexpr int kChainGrid = 512;         // workgroups of one instance (two per compute unit)
+
+// Spin until *p >= v (device-scope loads); false, with the error word set,
+// if the bound runs out or another workgroup of the launch gave up.
+__device__ __forceinline__ bool chain_wait(const int32_t *p, int32_t v, int32_t *err)
+{
+    int it = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (++it > kChainSpin) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+// Initial tile states and task counters of every chain launch, per instance.
+__global__ void k_chain_reset(int32_t *__restrict__ tstate, const int32_t *__restrict__ tinit,
+                              int32_t ntiles, int32_t *__restrict__ cticket, int32_t nchain)
+{
+    tstate += (int64_t)blockIdx.y * ntiles;
+    cticket += (int64_t)blockIdx.y * nchain;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ntiles; i += gridDim.x * blockDim.x)
+        tstate[i] = tinit[i];
+    if (blockIdx.x == 0)
+        for (int32_t i = threadIdx.x; i < nchain; i += blockDim.x) cticket[i] = 0;
+}
+
+// An nr x w block at src (leading dimension ld) into the 64 x 64 LDS block
+// dst (stride LDC), zero elsewhere; device-coherent loads.
+template <typename T>
+__device__ __forceinline__ void tile_in_coherent(T *dst, const T *src, int64_t ld, int nr, int w)
+{
+    const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+    const __amdgpu_buffer_rsrc_t rs = coherent_rsrc(src);
+    const uint32_t ldb = sizeof(T) * (uint32_t)ld;
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        const T x = coherent_ld<T>(rs, (uint32_t)min(c, w - 1) * ldb + sizeof(T) * (uint32_t)min(i, nr - 1));
+        v[u] = (i < nr && c < w) ? x : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) dst[(c0 + 4 * u) * LDC + i] = v[u];
+}
+
+template <typename T, typename U>
+__device__ __forceinline__ void tile_out_coherent(T *dst, const U *src, int64_t ld, int nr, int w)
+{
+    const int i = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+    const __amdgpu_buffer_rsrc_t rs = coherent_rsrc(dst);
+    const uint32_t ldb = sizeof(T) * (uint32_t)ld;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        if (i < nr && c < w) coherent_st<T>(rs, (uint32_t)c * ldb + sizeof(T) * (uint32_t)i, (T)src[c * LDC + i]);
+    }
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(NT, 2) void k_chain(const Task *__restrict__ tasks, int32_t ntasks,
+                                              const BlockDesc *__restrict__ blk,
+                                              const int32_t *__restrict__ tbase, int32_t *tstate,
+                                              int32_t ntiles, int32_t *cticket, int32_t nchain,
+                                              T *Lx, int32_t *__restrict__ info, int64_t lx_stride,
+                                              const double *__restrict__ pfloor, int32_t n)
+{
+    Lx += blockIdx.y * lx_stride;
+    info += 4 * blockIdx.y;
+    if (pfloor) pfloor += (int64_t)blockIdx.y * n;
+    tstate += (int64_t)blockIdx.y * ntiles;
+    int32_t *ticket = cticket + (int64_t)blockIdx.y * nchain;
+    int32_t *err = info + 2;
+    __shared__ double C[64 * LDC];      // a diagonal tile factored in FP64, or the tile X to solve
+    __shared__ T Dg[64 * LDC];          // the factored diagonal block of a solve
+    __shared__ T M[4 * 272];            // its inverted 16 x 16 diagonal triangles
+    __shared__ int s_t, s_ok;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    for (;;) {
+        __syncthreads();                // the previous task's LDS and s_t reads are done
+        if (tid == 0)
+            s_t = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? ntasks
+                                                                                   : atomicAdd(ticket, 1);
+        __syncthreads();
+        const int q = s_t;
+        if (q >= ntasks) break;
+        const Task tk = tasks[q];
+        const BlockDesc J = blk[tk.J];
+        const int r0 = tk.t * TR;
+        const int nr = min(TR, J.r - r0);
+        const int w = J.w;
+        T *LJ = Lx + J.valoff;
+        const int32_t tile = tbase[tk.J] + tk.t;
+        const bool factor = tk.flags & kFuseFactor;
+        const bool solve = tk.flags & kChainSolve;
+        typename Mfma<T>::acc_t acc[2][2] = {};
+        const bool active = 32 * wr < nr && 32 * wc < w;
+        if (tk.K >= 0) {
+            const BlockDesc K = blk[tk.K];
+            const int d = J.col0 - K.col0;
+            if (tid == 0) {
+                const int32_t kb = tbase[tk.K];
+                bool ok = chain_wait(&tstate[tile], tk.K, err);
+                for (int x = d / TR; ok && x <= (d + w - 1) / TR; ++x) ok = chain_wait(&tstate[kb + x], tk.K + 1, err);
+                for (int x = (d + r0) / TR; ok && x <= (d + r0 + nr - 1) / TR; ++x)
+                    ok = chain_wait(&tstate[kb + x], tk.K + 1, err);
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (!s_ok) break;
+            if (active) {
+                const __amdgpu_buffer_rsrc_t rt = coherent_rsrc(LJ + r0);
+                const uint32_t ldb = sizeof(T) * (uint32_t)J.ld;
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
+                            const int col = 32 * wc + 16 * nn + (lane & 15);
+                            const bool ok = row < nr && col < w;
+                            const T val = coherent_ld<T>(rt, (uint32_t)min(col, w - 1) * ldb +
+                                                                 sizeof(T) * (uint32_t)min(row, nr - 1));
+                            acc[m][nn][v] = ok ? val : T(0);
+                        }
+                const T *LK = Lx + K.valoff;
+                wave_product_pipe<T, OP, true>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
+            }
+        }
+        if (factor) {
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
+                            const int col = 32 * wc + 16 * nn + (lane & 15);
+                            if (row < nr && col < w) C[col * LDC + row] = (double)acc[m][nn][v];
+                        }
+            }
+            __syncthreads();
+            panel_factor<OP != kOpNative>(C, nr, w, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
+            tile_out_coherent(LJ + r0, C, J.ld, nr, w);
+        } else if (solve) {
+            T *X = reinterpret_cast<T *>(C);
+            if (tk.K >= 0) {
+                // the updated tile, zero outside its nr x w entries
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
+                            const int col = 32 * wc + 16 * nn + (lane & 15);
+                            X[col * LDC + row] = (active && row < nr && col < w) ? acc[m][nn][v] : T(0);
+                        }
+            } else {
+                tile_in_coherent(X, LJ + r0, J.ld, nr, w);
+            }
+            if (tid == 0) s_ok = chain_wait(&tstate[tbase[tk.J]], tk.J + 1, err);
+            __syncthreads();
+            if (!s_ok) break;
+            tile_in_coherent(Dg, LJ, J.ld, w, w);
+            __syncthreads();
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+            if (16 * wv < w) wave_tri_inverse(Dg, 16 * wv, min(16, w - 16 * wv), M + 272 * wv);
+            __syncthreads();
+            if (16 * wv < nr) wave_rows_solve(X, Dg, M, 16 * wv, w);
+            __syncthreads();
+            tile_out_coherent(LJ + r0, X, J.ld, nr, w);
+        } else if (active) {
+            const __amdgpu_buffer_rsrc_t rt = coherent_rsrc(LJ + r0);
+            const uint32_t ldb = sizeof(T) * (uint32_t)J.ld;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int nn = 0; nn < 2; ++nn)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 32 * wr + 16 * m + Mfma<T>::row(lane, v);
+                        const int col = 32 * wc + 16 * nn + (lane & 15);
+                        if (row < nr && col < w)
+                            coherent_st<T>(rt, (uint32_t)col * ldb + sizeof(T) * (uint32_t)row, acc[m][nn][v]);
+                    }
+        }
+        // every store of the task has completed before its state moves on
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(&tstate[tile], (factor || solve) ? tk.J + 1 : tk.K + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // The inverse of every diagonal block, for the triangular solves.  Its
 // strictly lower part is stored transposed in the block's upper triangle
 // (entry (i, j), i > j, at row j of column i), which the factorization
@@ -1589,9 +1847,24 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
                                                                       D.dscale, D.acoord, P.n);
         k_info_reset<<<dim3(1, m), 1, 0, s>>>(D.info);
     }
+    if (P.nchain > 0) {
+        Bracket b(prof, s, 0);
+        k_chain_reset<<<dim3(grid_for(P.tbase[P.nb]), m), 256, 0, s>>>(D.tstate, D.tinit, P.tbase[P.nb],
+                                                                       D.cticket, P.nchain);
+    }
+    int32_t chain = 0;
     for (const Phase &ph : P.phases) {
         const dim3 g((unsigned)(ph.t1 - ph.t0), m);
         Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
+        if (ph.kind == kPhaseChain) {
+            const int64_t nt = ph.t1 - ph.t0;
+            const unsigned gx = (unsigned)std::min<int64_t>(nt, std::max(16, kChainGrid / (int)m));
+            k_chain<T, OP><<<dim3(gx, m), NT, 0, s>>>(D.tasks + ph.t0, (int32_t)nt, D.blk, D.tbase, D.tstate,
+                                                      P.tbase[P.nb], D.cticket + chain, P.nchain, Lx, D.info,
+                                                      lxs, pfloor, P.n);
+            ++chain;
+            continue;
+        }
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
             k_external<T, true, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                      D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,

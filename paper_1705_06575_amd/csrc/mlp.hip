@@ -13,8 +13,9 @@
 //
 // Forward and the per-sample backward run one thread per sample with the
 // weights in LDS (every thread reads the same weight: broadcasts).  Each
-// gradient entry is then one thread's sum over all samples in sample order,
-// so gradients are bitwise reproducible.
+// gradient entry is then a sum over samples in a fixed order (chunks in
+// sample order, their sums in chunk order), so gradients are bitwise
+// reproducible.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -110,33 +111,48 @@ __global__ __launch_bounds__(256) void k_mlp_backward_samples(const float *__res
     DY[s] = dy;
 }
 
-// One thread per parameter: its gradient as a sum over samples in order.
+// Gradient entries as sums over samples, in two deterministic steps: the
+// samples are cut into kMlpGradChunks consecutive chunks, one thread per
+// (parameter, chunk) sums its chunk in sample order, and k_mlp_grad_sum
+// adds the chunk sums in chunk order.
 __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ X, int n, int D,
                                                   const float *__restrict__ work,
-                                                  float *__restrict__ grad)
+                                                  float *__restrict__ partial)
 {
     const int count = H * D + H + H * H + H + H + 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
+    const int len = (n + kMlpGradChunks - 1) / kMlpGradChunks;
+    const int a0 = min(n, (int)blockIdx.y * len), a1 = min(n, a0 + len);
     const float *H1 = work, *H2 = H1 + (int64_t)n * H, *D1 = H2 + (int64_t)n * H, *D2 = D1 + (int64_t)n * H;
     const float *DY = D2 + (int64_t)n * H;
     float s = 0.0f;
     int q = k;
     if (q < H * D) {                                  // W1[j][i] = sum dh1[j] x[i]
         const int j = q / D, i = q % D;
-        for (int a = 0; a < n; ++a) s += D1[(int64_t)a * H + j] * X[(int64_t)a * D + i];
+        for (int a = a0; a < a1; ++a) s += D1[(int64_t)a * H + j] * X[(int64_t)a * D + i];
     } else if ((q -= H * D) < H) {                    // b1[j]
-        for (int a = 0; a < n; ++a) s += D1[(int64_t)a * H + q];
+        for (int a = a0; a < a1; ++a) s += D1[(int64_t)a * H + q];
     } else if ((q -= H) < H * H) {                    // W2[j][i] = sum dh2[j] h1[i]
         const int j = q / H, i = q % H;
-        for (int a = 0; a < n; ++a) s += D2[(int64_t)a * H + j] * H1[(int64_t)a * H + i];
+        for (int a = a0; a < a1; ++a) s += D2[(int64_t)a * H + j] * H1[(int64_t)a * H + i];
     } else if ((q -= H * H) < H) {                    // b2[j]
-        for (int a = 0; a < n; ++a) s += D2[(int64_t)a * H + q];
+        for (int a = a0; a < a1; ++a) s += D2[(int64_t)a * H + q];
     } else if ((q -= H) < H) {                        // w3[j] = sum dy h2[j]
-        for (int a = 0; a < n; ++a) s += DY[a] * H2[(int64_t)a * H + q];
+        for (int a = a0; a < a1; ++a) s += DY[a] * H2[(int64_t)a * H + q];
     } else {                                          // b3
-        for (int a = 0; a < n; ++a) s += DY[a];
+        for (int a = a0; a < a1; ++a) s += DY[a];
     }
+    partial[(int64_t)blockIdx.y * count + k] = s;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_grad_sum(const float *__restrict__ partial, int count,
+                                                      float *__restrict__ grad)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    float s = 0.0f;
+    for (int c = 0; c < kMlpGradChunks; ++c) s += partial[(int64_t)c * count + k];
     grad[k] = s;
 }
 
@@ -156,6 +172,11 @@ __global__ void k_mlp_adam(float *__restrict__ p, const float *__restrict__ g, f
 
 int64_t mlp_param_count(int D) { return (int64_t)H * D + H + (int64_t)H * H + H + H + 1; }
 
+int64_t mlp_work_floats(int n, int D)
+{
+    return (int64_t)n * (4 * H + 1) + (int64_t)kMlpGradChunks * mlp_param_count(D);
+}
+
 hipError_t launch_mlp_forward(const float *params, const float *X, int n, int D, float *y,
                               hipStream_t s)
 {
@@ -173,7 +194,10 @@ hipError_t launch_mlp_backward(const float *params, const float *X, const float 
         const size_t lds = sizeof(float) * (size_t)count;
         k_mlp_backward_samples<<<(n + 255) / 256, 256, lds, s>>>(params, X, t, n, D, work);
     }
-    k_mlp_grad<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(X, n, D, work, grad);
+    float *partial = work + mlp_work_floats(n, D) - (int64_t)kMlpGradChunks * count;
+    const unsigned gx = (unsigned)((count + 255) / 256);
+    k_mlp_grad<<<dim3(gx, kMlpGradChunks), 256, 0, s>>>(X, n, D, work, partial);
+    k_mlp_grad_sum<<<gx, 256, 0, s>>>(partial, (int)count, grad);
     return hipGetLastError();
 }
 

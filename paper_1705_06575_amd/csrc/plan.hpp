@@ -101,6 +101,9 @@ static_assert(sizeof(WaveItem) == 32, "WaveItem layout is shared with the device
 static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
 constexpr int32_t kFuseFactor = 1;
+// A task of a chain launch (kPhaseChain) that ends by solving its tile
+// against its block's factored diagonal block (X := X L_JJ^{-T}).
+constexpr int32_t kChainSolve = 8;
 // A long external-update tile is split into parts (tasks of the same launch
 // with kPartial and K = index of their PartDesc): each part accumulates
 // its share of the products into a partial tile; the part that finishes
@@ -133,10 +136,16 @@ static_assert(sizeof(PartDesc) == 16, "PartDesc layout is shared with the device
 constexpr int kVariants = 4;
 constexpr int32_t kVariantLarge[kVariants] = {1 << 30, 64, 32, 0};
 constexpr uint8_t kVariantStaged = 3;
-constexpr int kSuperFeatures = 8;   // features of a device supernode, see Plan::sfeat
+constexpr int kSuperFeatures = 12;  // features of a device supernode, see Plan::sfeat
 
-// One kernel launch of the factorization.
-enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2 };
+// One kernel launch of the factorization.  A chain launch runs, for the
+// supernodes of one level, the off-diagonal solves of their first blocks
+// and every right-looking step inside them (update by the previous block,
+// then factorization or solve of the next block's tiles) as one persistent
+// launch whose tasks wait for the tiles they read (Plan::tbase; only with
+// Plan::chain_launch); by default every step is a kPhaseInternal launch
+// followed by a kPhaseTrsm launch.
+enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2, kPhaseChain = 3 };
 struct Phase {
     int32_t kind;
     int64_t t0, t1;     // task range in Plan::ftasks
@@ -190,6 +199,7 @@ struct Plan {
     double split_share = kSplitShare;  // a long external tile's part: max(kSplitUnits, level cost / share)
     double pivot_floor = 0.0;   // tau: pivots below tau times their scaled diagonal entry are
                                 // replaced by it (scaled precisions only; 0 = never)
+    bool chain_launch = false;  // the steps inside a level's supernodes as one persistent launch
     double analyze_ms = 0.0;
 
     // ---- ordering and column structure (permuted numbering)
@@ -252,7 +262,10 @@ struct Plan {
     // features a cost model sees (kSuperFeatures each): width, rows, row
     // tiles of its blocks, incidences it receives, their product flops,
     // the fractions of those flops in incidences of >= 64 and >= 32 rows,
-    // columns and inner indices, and its level
+    // columns and inner indices, its level; then the level's context (the
+    // supernodes it shares its launches with): the level's update flops,
+    // its supernode count, its row tiles receiving updates, and this
+    // supernode's share of the level's update flops
     std::vector<uint8_t> svariant;
     std::vector<double> sfeat;
     std::vector<int32_t> task_super;    // ftasks.size(): target supernode of external tasks, else -1
@@ -270,6 +283,15 @@ struct Plan {
     int32_t nslevels = 0;
     std::vector<Task> ftasks;       // all factor tasks in launch order
     std::vector<Phase> phases;      // launches
+    // tiles of the chain launches: tile t of block J is tile tbase[J] + t
+    // (every block's 64-row tiles, ceil(r / 64) each); the state of a tile
+    // counts the operations done on it: it starts at b0, the first block of
+    // the tile's supernode (b0 + 1 for tile 0 of block b0, factored by the
+    // external launch), becomes K + 1 once block K's update has been
+    // applied, and J + 1 once the tile is final (factored or solved).
+    std::vector<int32_t> tbase;     // nb + 1
+    std::vector<int32_t> tinit;     // tbase[nb]: initial states
+    int32_t nchain = 0;             // chain launches
     std::vector<int64_t> iptr;      // ftasks.size()+1: incidences of external-update tasks
     std::vector<int64_t> ibig;      // ftasks.size(): end of each task's leading large incidences
     std::vector<uint8_t> phase_coop;// per phase: an external phase with large incidences

@@ -240,6 +240,110 @@ void build_schedule(Plan &P)
         P.incs.push_back(in);
         P.ext_operand_entries += (double)(in.nI + in.nJ) * (double)ri.wk;
     };
+    // tiles of the chain launches and their initial states
+    P.tbase.assign((size_t)P.nb + 1, 0);
+    for (int32_t J = 0; J < P.nb; ++J) P.tbase[J + 1] = P.tbase[J] + ntiles(J);
+    P.tinit.assign((size_t)P.tbase[P.nb], 0);
+    for (int32_t r = 0; r < P.nds; ++r) {
+        const int32_t b0 = P.sbptr[r];
+        for (int32_t J = b0; J < P.sbptr[r + 1]; ++J)
+            for (int32_t q = P.tbase[J]; q < P.tbase[J + 1]; ++q) P.tinit[q] = b0;
+        P.tinit[P.tbase[b0]] = b0 + 1;
+    }
+    P.nchain = 0;
+    // One chain launch for level l: the off-diagonal tiles of each
+    // supernode's first block solve against its diagonal block (factored by
+    // the external launch), and for k = 1, 2, ... every tile of blocks
+    // b0 + k, b0 + k + 1, ... subtracts block b0 + k - 1's product, block
+    // b0 + k's tile 0 is then factored and its other tiles solved.  A task
+    // needs its tile's previous update and the final tiles of the source
+    // block it reads (those holding the target block's columns and the
+    // tile's rows); a solve also needs the factored diagonal tile.  Tasks
+    // are ordered by their earliest start when every task has a workgroup
+    // (unit time per update, a factorization 3 more, a solve 1 more): the
+    // critical chain of factorizations leads, and every task comes after
+    // those it waits for, so a persistent launch that hands out tasks in
+    // this order never waits for a task no workgroup holds.
+    std::vector<double> tcur, tfin;
+    std::vector<int32_t> chain_check;
+    auto emit_chain = [&](int32_t l) {
+        struct CT {
+            Task tk;
+            double start;
+        };
+        std::vector<CT> ct;
+        tcur.assign((size_t)P.tbase[P.nb], 0.0);
+        tfin.assign((size_t)P.tbase[P.nb], 0.0);
+        constexpr double dU = 1.0, dF = 3.0, dT = 1.0;
+        for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
+            const int32_t s2 = sl_list[q];
+            const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
+            for (int32_t t = 1; t < ntiles(b0); ++t) {
+                ct.push_back(CT{Task{b0, t, -1, kChainSolve}, 0.0});
+                tfin[P.tbase[b0] + t] = dT;
+            }
+            for (int32_t k = 1; k < nbs; ++k) {
+                const int32_t K = b0 + k - 1;
+                const BlockDesc &dK = P.blk[K];
+                for (int32_t c = k; c < nbs; ++c) {
+                    const int32_t J = b0 + c;
+                    const BlockDesc &dJ = P.blk[J];
+                    const int32_t d = dJ.col0 - dK.col0;
+                    for (int32_t t = 0; t < ntiles(J); ++t) {
+                        const int32_t r0 = t * kTileRows, nr = std::min(kTileRows, dJ.r - r0);
+                        const int32_t tile = P.tbase[J] + t;
+                        double st = tcur[tile];
+                        for (int32_t x = d / kTileRows; x <= (d + dJ.w - 1) / kTileRows; ++x)
+                            st = std::max(st, tfin[P.tbase[K] + x]);
+                        for (int32_t x = (d + r0) / kTileRows; x <= (d + r0 + nr - 1) / kTileRows; ++x)
+                            st = std::max(st, tfin[P.tbase[K] + x]);
+                        int32_t flags = 0;
+                        double dur = dU;
+                        if (c == k && t == 0) {
+                            flags = kFuseFactor;
+                            dur += dF;
+                        } else if (c == k) {
+                            st = std::max(st, tfin[P.tbase[J]] - dU);   // the solve waits, not the update
+                            flags = kChainSolve;
+                            dur += dT;
+                        }
+                        ct.push_back(CT{Task{J, t, K, flags}, st});
+                        tcur[tile] = st + dur;
+                        if (c == k) tfin[tile] = std::max(st + dur, tfin[P.tbase[J]] + dT);
+                    }
+                }
+            }
+        }
+        if (ct.empty()) return;
+        std::stable_sort(ct.begin(), ct.end(), [](const CT &a, const CT &b) { return a.start < b.start; });
+        // the launch's tasks run one after another in this order without a
+        // wait that is not already met (so the persistent launch cannot
+        // wait for a task that no workgroup holds)
+        std::vector<int32_t> &st = chain_check;
+        st = P.tinit;
+        for (const CT &c : ct) {
+            const Task &tk = c.tk;
+            const BlockDesc &dJ = P.blk[tk.J];
+            const int32_t tile = P.tbase[tk.J] + tk.t;
+            bool ok = true;
+            if (tk.K >= 0) {
+                const int32_t d = dJ.col0 - P.blk[tk.K].col0, r0 = tk.t * kTileRows;
+                const int32_t nr = std::min(kTileRows, dJ.r - r0);
+                ok = st[tile] == tk.K;
+                for (int32_t x = d / kTileRows; x <= (d + dJ.w - 1) / kTileRows; ++x)
+                    ok = ok && st[P.tbase[tk.K] + x] >= tk.K + 1;
+                for (int32_t x = (d + r0) / kTileRows; x <= (d + r0 + nr - 1) / kTileRows; ++x)
+                    ok = ok && st[P.tbase[tk.K] + x] >= tk.K + 1;
+            }
+            if (tk.flags & kChainSolve) ok = ok && st[P.tbase[tk.J]] >= tk.J + 1;
+            if (!ok) throw std::logic_error("chain launch order");
+            st[tile] = (tk.flags & (kFuseFactor | kChainSolve)) ? tk.J + 1 : tk.K + 1;
+        }
+        open_phase(kPhaseChain);
+        for (const CT &c : ct) push_task(c.tk.J, c.tk.t, c.tk.K, c.tk.flags, 0);
+        close_phase();
+        P.nchain++;
+    };
     std::vector<const RawInc *> small;
     struct Pending {
         int32_t J, t, s2;
@@ -366,6 +470,10 @@ void build_schedule(Plan &P)
             }
         }
         close_phase();
+        if (P.chain_launch) {
+            emit_chain(l);
+            continue;
+        }
         open_phase(kPhaseTrsm);
         for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
             const int32_t J = P.sbptr[sl_list[q]];
@@ -415,6 +523,24 @@ void build_schedule(Plan &P)
         ft[5] = ft[4] > 0 ? ft[5] / ft[4] : 0.0;
         ft[6] = ft[4] > 0 ? ft[6] / ft[4] : 0.0;
         ft[7] = P.slevel[s2];
+    }
+    {
+        std::vector<double> lflops((size_t)P.nslevels, 0.0), lcount((size_t)P.nslevels, 0.0),
+            ltiles((size_t)P.nslevels, 0.0);
+        for (int32_t s2 = 0; s2 < P.nds; ++s2) {
+            const double *ft = P.sfeat.data() + (size_t)s2 * kSuperFeatures;
+            lflops[P.slevel[s2]] += ft[4];
+            lcount[P.slevel[s2]] += 1.0;
+            ltiles[P.slevel[s2]] += ft[2];
+        }
+        for (int32_t s2 = 0; s2 < P.nds; ++s2) {
+            double *ft = P.sfeat.data() + (size_t)s2 * kSuperFeatures;
+            const int32_t l = P.slevel[s2];
+            ft[8] = lflops[l];
+            ft[9] = lcount[l];
+            ft[10] = ltiles[l];
+            ft[11] = lflops[l] > 0 ? ft[4] / lflops[l] : 0.0;
+        }
     }
     P.task_super.assign(P.ftasks.size(), -1);
     for (const Phase &ph : P.phases)

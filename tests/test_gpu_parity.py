@@ -253,6 +253,40 @@ def test_factor_is_bitwise_deterministic(S, torch_cuda):
     assert np.array_equal(L1.view(np.uint64), L2.view(np.uint64))
 
 
+@pytest.mark.parametrize("prec,B", [("f64", 64), ("f32", 64), ("bf16", 64), ("f64", 32)])
+def test_chain_launch_matches_step_launches(S, orc, torch_cuda, prec, B):
+    """The persistent per-level chain launch (tasks waiting for the tiles
+    they read, device-coherent handoffs) gives the step launches' factor
+    bit for bit, on a pattern with wide supernodes (several blocks); a
+    batch's solves agree to rounding; the FP64 factor equals the oracle."""
+    torch = torch_cuda
+    w = W.config2(24)
+    Ax = torch.from_numpy(w.Ax).cuda()
+    out = {}
+    for chain in (False, True):
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision=prec, block_width=B, chain_launch=chain)
+        an.factor(Ax)
+        assert an.status() == 0
+        out[chain] = (an.export_factor(), int(an.stat("nphases")))
+        X = np.stack([w.Ax, 2.0 * w.Ax, w.Ax + 1.0 * (w.Ai == np.repeat(np.arange(w.n), np.diff(w.Ap)))])
+        bt = S.Batch(an, 3)
+        bt.factor(torch.from_numpy(X).cuda())
+        assert (bt.status() == 0).all()
+        R = torch.from_numpy(np.random.default_rng(8).uniform(-1.0, 1.0, (3, w.n))).cuda()
+        out[(chain, "batch")] = bt.solve_(R).cpu().numpy()
+        bt.close()
+    _say(f"case chain {prec} B{B}: launches {out[False][1]} -> {out[True][1]}")
+    assert out[True][1] < out[False][1]
+    assert np.array_equal(out[True][0], out[False][0])
+    # the sweeps add with atomics (order not fixed), so the batch's solves
+    # agree to rounding, not bit for bit
+    xb, xs = out[(True, "batch")], out[(False, "batch")]
+    assert np.linalg.norm(xb - xs) <= 1e-10 * np.linalg.norm(xs)
+    if prec == "f64":
+        f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+        assert np.linalg.norm(out[True][0] - f["Lx"]) <= 1e-12 * np.linalg.norm(f["Lx"])
+
+
 @pytest.mark.parametrize("m", [12, 24])
 def test_grid3d_scaled(S, orc, torch_cuda, m):
     w = W.config2(m)

@@ -249,6 +249,43 @@ def test_kind_flops_partition_the_method_count(S):
             assert sum(kf.values()) == an.stat("flops")
 
 
+def test_chain_launch_schedule(S):
+    """With the per-level chain launch the analysis checks on the host that
+    the launch's tasks, run one after another in their order, never wait
+    (it fails with SYM_ESCHED otherwise); the schedule then has one launch
+    per level where the step launches have one per step and kind, and the
+    same method flop count."""
+    for w in [W.config2(20), W.knn_instance(3, nv=2500), W.random_spd(300, 1.0, np.random.default_rng(4))]:
+        for B in (16, 32, 64):
+            a = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", block_width=B)
+            c = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", block_width=B, chain_launch=True)
+            assert c.stat("nphases") <= a.stat("nphases")
+            assert c.stat("flops") == a.stat("flops")
+            assert c.kind_flops() == a.kind_flops()
+
+
+def test_supernode_features(S):
+    """The cost model's features: sizes match the device supernodes, the
+    update flops (whole tile products, so at least the external-update
+    share of the method count) cover that share, the flop fractions lie in
+    [0, 1], and the level context is the level's sums of the supernodes'
+    own features."""
+    w = W.knn_instance(4, nv=1500)
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd")
+    f = an.get("super_feat").reshape(-1, 12)
+    nds = int(an.stat("ndsuper"))
+    assert f.shape[0] == nds
+    assert f[:, 0].sum() == w.n and (f[:, 0] >= 1).all() and (f[:, 1] >= f[:, 0]).all()
+    assert ((f[:, 5] >= 0) & (f[:, 5] <= f[:, 6]) & (f[:, 6] <= 1)).all()
+    assert f[:, 4].sum() >= an.kind_flops()["external"] > 0
+    for lv in np.unique(f[:, 7]):
+        m = f[:, 7] == lv
+        assert np.allclose(f[m, 8], f[m, 4].sum()) and (f[m, 9] == m.sum()).all()
+        assert (f[m, 10] == f[m, 2].sum()).all()
+        share = f[m, 4] / f[m, 4].sum() if f[m, 4].sum() > 0 else np.zeros(m.sum())
+        assert np.allclose(f[m, 11], share)
+
+
 class _Pat:
     """A pattern with dummy values, for the symbolic comparisons."""
 

@@ -403,6 +403,28 @@ def knn_instance(k: int, nv: int | None = None, knn: int = 13) -> Workload:
                     np.ascontiguousarray(vals), perm, ())
 
 
+
+KNN_FAMILY = 50             # instances 0..49 of the k-NN family
+
+
+def knn_size(k: int) -> int:
+    """Vertex count of k-NN instance k (the first draw of its stream, as in
+    knn_instance with nv=None): log-uniform in [20000, 200000]."""
+    rng = rng_for_instance(1000 + k)
+    return int(np.exp(rng.uniform(np.log(20000), np.log(200000))))
+
+
+def knn_split():
+    """The seeded subset of the 50-instance k-NN family used for the
+    learned cost model.  Instances are ranked by vertex count; ranks
+    0, 5, ..., 45 and the largest (rank 49) train the model (21.9k to
+    200k vertices), rank 17 (46k vertices) is the held-out test instance
+    and rank 28 (83k vertices) the held-out benchmark instance.  Returns
+    {"train": [k, ...], "test": k, "bench": k}."""
+    order = sorted(range(KNN_FAMILY), key=knn_size)
+    return {"train": [order[r] for r in list(range(0, 50, 5)) + [49]],
+            "test": order[17], "bench": order[28]}
+
 # --------------------------------------------------------------------------
 # right-hand sides
 # --------------------------------------------------------------------------
