@@ -25,7 +25,7 @@ struct DevicePlan {
     int64_t *ibig = nullptr;        // tasks: end of each task's leading large incidences
     Incidence *incs = nullptr;      // (tile, descendant) incidences
     uint8_t *imap = nullptr;        // their tile-relative rows and columns
-    int64_t *wptr = nullptr;        // 4*tasks+1: wavefront item ranges
+    int64_t *wptr = nullptr;        // 16*tasks+1: wavefront item ranges by row-block group
     WaveItem *witems = nullptr;     // small incidences per wavefront
     uint8_t *wmap = nullptr;        // their tile-relative rows and columns
     int64_t *cptr = nullptr;        // tasks+1: staged chunk ranges

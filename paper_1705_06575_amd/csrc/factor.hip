@@ -871,10 +871,13 @@ __device__ __forceinline__ void coop_product_packed(float *C, uint64_t (*As)[4][
 
 // ---- wavefront items (small incidences)
 //
-// A wavefront runs its item list as one stream of operand batches.  A batch
-// covers kSteps k-steps of 4 (k = 4 (kb + s) + l / 16 for lane l): per step
-// four A values (product rows 16m + l % 16, m < 4) and one B value (product
-// column l % 16).  Addresses are clamped into the item's rows, columns and
+// A wavefront runs its item list as up to four streams of operand batches,
+// one per group of items with the same number NRB of 16-row blocks (the
+// analysis groups them), so that no load or product is spent on row blocks
+// an item does not have.  A batch covers kSteps k-steps of 4 (k = 4 (kb +
+// s) + l / 16 for lane l): per step NRB A values (product rows 16m + l % 16,
+// m < NRB) and one B value (product column l % 16).  Addresses are clamped
+// into the item's rows, columns and
 // k range, so every load is in bounds, none depends on another load's value
 // and every batch issues the same loads unconditionally (the hardware's
 // in-order load counter then lets the products of one batch wait for that
@@ -909,17 +912,16 @@ __device__ __forceinline__ Item load_item(const WaveItem *__restrict__ items, in
     return it;
 }
 
-template <typename T>
+template <typename T, int NRB>
 struct Batch {
-    T a[kSteps][4];
+    T a[kSteps][NRB];
     T b[kSteps];
     int lr, cc;         // tile row of product row `lane`, tile column of product column lane % 16
 };
 
-__device__ __forceinline__ int item_nrb(const Item &it) { return (it.nI + 15) >> 4; }
-
-template <typename T>
-__device__ __forceinline__ void issue(Batch<T> &r, const T *__restrict__ Lx,
+// The loads of one batch of an item with NRB blocks of 16 product rows.
+template <typename T, int NRB>
+__device__ __forceinline__ void issue(Batch<T, NRB> &r, const T *__restrict__ Lx,
                                       const uint8_t *__restrict__ wmap, const Item &it, int kb,
                                       int lane)
 {
@@ -934,23 +936,22 @@ __device__ __forceinline__ void issue(Batch<T> &r, const T *__restrict__ Lx,
     const uint32_t ldb = sizeof(T) * (uint32_t)it.ld;
     const int wk1 = it.wk - 1;
     const uint32_t ob = sizeof(T) * (uint32_t)(it.a0 + min(li, it.nJ - 1));
-    uint32_t oa[4];
+    uint32_t oa[NRB];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) oa[m] = sizeof(T) * (uint32_t)(it.b0 + min(16 * m + li, it.nI - 1));
+    for (int m = 0; m < NRB; ++m) oa[m] = sizeof(T) * (uint32_t)(it.b0 + min(16 * m + li, it.nI - 1));
 #pragma unroll
     for (int s = 0; s < kSteps; ++s) {
         const uint32_t ko = (uint32_t)min(4 * (kb + s) + kq, wk1) * ldb;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) r.a[s][m] = *reinterpret_cast<const T *>(base + (oa[m] + ko));
+        for (int m = 0; m < NRB; ++m) r.a[s][m] = *reinterpret_cast<const T *>(base + (oa[m] + ko));
         r.b[s] = *reinterpret_cast<const T *>(base + (ob + ko));
     }
 }
 
-template <typename T, int OP>
-__device__ __forceinline__ void compute(const Batch<T> &r, typename Mfma<T>::acc_t (&acc)[4],
+template <typename T, int OP, int NRB>
+__device__ __forceinline__ void compute(const Batch<T, NRB> &r, typename Mfma<T>::acc_t (&acc)[NRB],
                                         const Item &it, int kb, int lane)
 {
-    const int nrb = item_nrb(it);
     if constexpr (OP == kOpNative) {
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
@@ -958,8 +959,7 @@ __device__ __forceinline__ void compute(const Batch<T> &r, typename Mfma<T>::acc
                 const bool vk = 4 * (kb + s) + (lane >> 4) < it.wk;
                 const T b = vk ? r.b[s] : T(0);
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    if (m < nrb) acc[m] = Mfma<T>::mma(r.a[s][m], b, acc[m]);
+                for (int m = 0; m < NRB; ++m) acc[m] = Mfma<T>::mma(r.a[s][m], b, acc[m]);
             }
         }
     } else {
@@ -970,11 +970,9 @@ __device__ __forceinline__ void compute(const Batch<T> &r, typename Mfma<T>::acc
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) b[s] = 4 * (kb + s) + (lane >> 4) < it.wk ? r.b[s] : 0.0f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m < nrb) {
-                const float a[4] = {r.a[0][m], r.a[1][m], r.a[2][m], r.a[3][m]};
-                acc[m] = mma_pack<OP>(a, b, acc[m]);
-            }
+        for (int m = 0; m < NRB; ++m) {
+            const float a[4] = {r.a[0][m], r.a[1][m], r.a[2][m], r.a[3][m]};
+            acc[m] = mma_pack<OP>(a, b, acc[m]);
         }
     }
 }
@@ -982,36 +980,36 @@ __device__ __forceinline__ void compute(const Batch<T> &r, typename Mfma<T>::acc
 // Subtract an item's finished product from the LDS tile and clear the
 // accumulators.  The tile row of product row i is lane i's lr; the tile
 // column of lane l's products is its own cc.
-template <typename T>
-__device__ __forceinline__ void scatter(T *C, typename Mfma<T>::acc_t (&acc)[4], const Batch<T> &r,
-                                        const Item &it, int r0, int nr, int w, int lane)
+template <typename T, int NRB>
+__device__ __forceinline__ void scatter(T *C, typename Mfma<T>::acc_t (&acc)[NRB],
+                                        const Batch<T, NRB> &r, const Item &it, int r0, int nr,
+                                        int w, int lane)
 {
-    const int nrb = item_nrb(it);
     const int cc = r.cc;
     const bool vc = (lane & 15) < it.nJ && cc < w;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        if (m < nrb) {
+    for (int m = 0; m < NRB; ++m) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * m + Mfma<T>::row(lane, v);
-                const int R = __shfl(r.lr, row);
-                if (vc && row < it.nI && R < nr && r0 + R >= cc) C[cc * LDC + R] -= acc[m][v];
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * m + Mfma<T>::row(lane, v);
+            const int R = __shfl(r.lr, row);
+            if (vc && row < it.nI && R < nr && r0 + R >= cc) C[cc * LDC + R] -= acc[m][v];
         }
         acc[m] = typename Mfma<T>::acc_t{};
     }
 }
 
-template <typename T, int OP>
+// One wavefront's items of NRB blocks of 16 product rows each (the items
+// of a group have 16 NRB - 15 to 16 NRB rows), as one pipelined stream.
+template <typename T, int OP, int NRB>
 __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ items,
                                            const uint8_t *__restrict__ wmap,
                                            const T *__restrict__ Lx, int64_t i0, int64_t i1, int r0,
                                            int nr, int w)
 {
     const int lane = threadIdx.x & 63;
-    Batch<T> X, Y;
-    typename Mfma<T>::acc_t acc[4] = {};
+    Batch<T, NRB> X, Y;
+    typename Mfma<T>::acc_t acc[NRB] = {};
     Item cur = load_item(items, i0);
     int64_t inx = i0 + 1;                  // index of the prefetched record `nxt`
     Item nxt = load_item(items, min(inx, i1 - 1));
@@ -1020,7 +1018,7 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
     // multiply batch P (item cur, k-steps from kb) while the following batch
     // loads into Q (after the last batch, a harmless reload); false once P
     // was the last batch
-    auto step = [&](Batch<T> &P, Batch<T> &Q) -> bool {
+    auto step = [&](Batch<T, NRB> &P, Batch<T, NRB> &Q) -> bool {
         const bool same = 4 * (kb + kSteps) < cur.wk;
         const bool more = same || inx < i1;
         const Item ni = same ? cur : nxt;
@@ -1030,7 +1028,7 @@ __device__ __forceinline__ void wave_items(T *C, const WaveItem *__restrict__ it
             ++inx;
             nxt = load_item(items, min(inx, i1 - 1));
         }
-        compute<T, OP>(P, acc, cur, kb, lane);
+        compute<T, OP, NRB>(P, acc, cur, kb, lane);
         if (!same) scatter(C, acc, P, cur, r0, nr, w, lane);
         cur = ni;
         kb = nkb;
@@ -1305,8 +1303,11 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
 
     // the small incidences: each wavefront runs its own item list
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int64_t i0 = wptr[4 * blockIdx.x + wv], i1 = wptr[4 * blockIdx.x + wv + 1];
-    if (i0 < i1) wave_items<T, OP>(C, witems, wmap, (const T *)Lx, i0, i1, r0, nr, w);
+    const int64_t *wg = wptr + 16 * (int64_t)blockIdx.x + 4 * wv;
+    if (wg[0] < wg[1]) wave_items<T, OP, 4>(C, witems, wmap, (const T *)Lx, wg[0], wg[1], r0, nr, w);
+    if (wg[1] < wg[2]) wave_items<T, OP, 3>(C, witems, wmap, (const T *)Lx, wg[1], wg[2], r0, nr, w);
+    if (wg[2] < wg[3]) wave_items<T, OP, 2>(C, witems, wmap, (const T *)Lx, wg[2], wg[3], r0, nr, w);
+    if (wg[3] < wg[4]) wave_items<T, OP, 1>(C, witems, wmap, (const T *)Lx, wg[3], wg[4], r0, nr, w);
     __syncthreads();
 
     bool finish = !partial;
@@ -1867,13 +1868,13 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
         }
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
             k_external<T, true, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
-                                                     D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
+                                                     D.incs, D.imap, D.wptr + 16 * ph.t0, D.witems,
                                                      D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                      D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
                                                      pfloor, P.n, D.cptr + ph.t0, D.chunks);
         else if (ph.kind == kPhaseExternal)
             k_external<T, false, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
-                                                      D.incs, D.imap, D.wptr + 4 * ph.t0, D.witems,
+                                                      D.incs, D.imap, D.wptr + 16 * ph.t0, D.witems,
                                                       D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                       D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
                                                       pfloor, P.n, D.cptr + ph.t0, D.chunks);

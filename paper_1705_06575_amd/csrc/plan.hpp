@@ -298,8 +298,10 @@ struct Plan {
     std::vector<Incidence> incs;
     std::vector<uint8_t> imap;      // tile-relative rows and columns of every incidence
     // the remaining (small) incidences as per-wavefront items: wavefront v of
-    // task q runs items [wptr[4q + v], wptr[4q + v + 1])
-    std::vector<int64_t> wptr;      // 4 * ftasks.size() + 1
+    // task q runs items [wptr[16q + 4v], wptr[16q + 4v + 4]), in four groups
+    // by row blocks: [wptr[16q + 4v + g], wptr[16q + 4v + g + 1]) holds the
+    // items of 4 - g blocks of 16 rows
+    std::vector<int64_t> wptr;      // 16 * ftasks.size() + 1
     std::vector<WaveItem> witems;
     std::vector<uint8_t> wmap;
     // staged tasks: chunks [cptr[q], cptr[q + 1]) of task q

@@ -50,6 +50,13 @@ __global__ void k_red_reset(double *red)
     if (threadIdx.x < 4) red[4 * blockIdx.y + threadIdx.x] = 0.0;
 }
 
+// Batched use: instance i owns 4 reduction words, its vectors start n
+// entries apart, its A values nnzA apart.  A thread takes one row for G
+// consecutive instances (workgroup row blockIdx.y holds instances
+// G blockIdx.y ...), so the row's pattern (positions and columns) is read
+// once for all G; each instance's sum runs over the row in the same order
+// as with G = 1.
+template <int G>
 __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col,
                                                   const int64_t *__restrict__ val,
@@ -57,37 +64,50 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
                                                   const double *__restrict__ b,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ r, double *__restrict__ red,
-                                                  int32_t n, int with_anorm, int64_t nnzA)
+                                                  int32_t n, int with_anorm, int64_t nnzA, int32_t m)
 {
-    Ax += blockIdx.y * nnzA;
-    b += (int64_t)blockIdx.y * n;
-    x += (int64_t)blockIdx.y * n;
-    r += (int64_t)blockIdx.y * n;
-    red += 4 * blockIdx.y;
-    double mr = 0.0, ma = 0.0, mx = 0.0, mb = 0.0;
+    const int32_t g0 = (int32_t)blockIdx.y * G;
+    double mr[G], ma[G], mx[G], mb[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) mr[g] = ma[g] = mx[g] = mb[g] = 0.0;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double s = 0.0, sa = 0.0;
+        double s[G], sa[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) s[g] = sa[g] = 0.0;
         for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            const double a = Ax[val[p]];
-            s += a * x[col[p]];
-            sa += fabs(a);
+            const int64_t v = val[p];
+            const int32_t c = col[p];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int64_t gi = min(g0 + g, m - 1);
+                const double a = Ax[gi * nnzA + v];
+                s[g] += a * x[gi * n + c];
+                sa[g] += fabs(a);
+            }
         }
-        const double ri = b[i] - s;
-        r[i] = ri;
-        mr = nan_max(mr, fabs(ri));
-        ma = nan_max(ma, sa);
-        mx = nan_max(mx, fabs(x[i]));
-        mb = nan_max(mb, fabs(b[i]));
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g0 + g < m) {
+                const int64_t o = (int64_t)(g0 + g) * n + i;
+                const double ri = b[o] - s[g];
+                r[o] = ri;
+                mr[g] = nan_max(mr[g], fabs(ri));
+                ma[g] = nan_max(ma[g], sa[g]);
+                mx[g] = nan_max(mx[g], fabs(x[o]));
+                mb[g] = nan_max(mb[g], fabs(b[o]));
+            }
+        }
     }
-    mr = wave_max(mr);
-    ma = wave_max(ma);
-    mx = wave_max(mx);
-    mb = wave_max(mb);
-    if ((threadIdx.x & 63) == 0) {
-        atomic_max_nonneg(&red[0], mr);
-        if (with_anorm) atomic_max_nonneg(&red[1], ma);
-        atomic_max_nonneg(&red[2], mx);
-        atomic_max_nonneg(&red[3], mb);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double wr = wave_max(mr[g]), wa = wave_max(ma[g]), wx = wave_max(mx[g]), wb = wave_max(mb[g]);
+        if ((threadIdx.x & 63) == 0 && g0 + g < m) {
+            double *rd = red + 4 * (int64_t)(g0 + g);
+            atomic_max_nonneg(&rd[0], wr);
+            if (with_anorm) atomic_max_nonneg(&rd[1], wa);
+            atomic_max_nonneg(&rd[2], wx);
+            atomic_max_nonneg(&rd[3], wb);
+        }
     }
 }
 
@@ -170,9 +190,12 @@ hipError_t launch_residual(const Plan &P, const DevicePlan &D, const double *Ax,
 {
     const unsigned m = (unsigned)D.m;
     k_red_reset<<<dim3(1, m), 64, 0, s>>>(D.red);
-    if (P.n > 0)
-        k_residual<<<dim3(grid_for(P.n), m), 256, 0, s>>>(D.arowptr, D.acol, D.aval, Ax, b, x, r,
-                                                          D.red, P.n, with_anorm ? 1 : 0, P.nnzA);
+    if (P.n > 0 && m >= 4)
+        k_residual<4><<<dim3(grid_for(P.n), (m + 3) / 4), 256, 0, s>>>(
+            D.arowptr, D.acol, D.aval, Ax, b, x, r, D.red, P.n, with_anorm ? 1 : 0, P.nnzA, (int32_t)m);
+    else if (P.n > 0)
+        k_residual<1><<<dim3(grid_for(P.n), m), 256, 0, s>>>(
+            D.arowptr, D.acol, D.aval, Ax, b, x, r, D.red, P.n, with_anorm ? 1 : 0, P.nnzA, (int32_t)m);
     return hipGetLastError();
 }
 

@@ -127,7 +127,7 @@ void build_schedule(Plan &P)
         P.iptr.push_back((int64_t)P.incs.size());
         P.ibig.push_back(big_end);
         P.cptr.push_back((int64_t)P.chunks.size());
-        while ((int64_t)P.wptr.size() < 4 * (int64_t)P.ftasks.size() + 1)
+        while ((int64_t)P.wptr.size() < 16 * (int64_t)P.ftasks.size() + 1)
             P.wptr.push_back((int64_t)P.witems.size());
     };
     // tile rows of K's rows [b0, b1) and tile columns of K's rows [a0, a1)
@@ -149,8 +149,14 @@ void build_schedule(Plan &P)
         for (int32_t q = ri.a0; q < ri.a1; ++q) crel.push_back((uint8_t)(rK[q] - dJ.col0));
     };
     // the wavefront items of one task's small incidences, wavefront-major
+    // Each wavefront's items are grouped by their 16-row blocks (4, 3, 2,
+    // then 1; list order within a group), so the kernel runs each group
+    // with loads and products for exactly that many row blocks; wptr holds
+    // 16 boundaries per task (wavefront v, group g: entry 4 v + g).
+    std::vector<WaveItem> wgroup[4];
     auto emit_wave_items = [&](int32_t J, int32_t t, const std::vector<const RawInc *> &small) {
         for (int32_t v = 0; v < 4; ++v) {
+            for (auto &g : wgroup) g.clear();
             for (const RawInc *ri : small) {
                 relative(J, t, *ri);
                 // columns are increasing: the wavefront's are a contiguous run
@@ -170,10 +176,13 @@ void build_schedule(Plan &P)
                 it.nJ = (uint8_t)(jhi - jlo);
                 P.wmap.insert(P.wmap.end(), rrel.begin(), rrel.end());
                 P.wmap.insert(P.wmap.end(), crel.begin() + jlo, crel.begin() + jhi);
-                P.witems.push_back(it);
+                wgroup[4 - (it.nI + 15) / 16].push_back(it);
                 P.ext_operand_entries += (double)(it.nI + it.nJ) * (double)ri->wk;
             }
-            P.wptr.push_back((int64_t)P.witems.size());
+            for (const auto &g : wgroup) {
+                P.witems.insert(P.witems.end(), g.begin(), g.end());
+                P.wptr.push_back((int64_t)P.witems.size());
+            }
         }
     };
     // the staged chunks of one tile's incidences (all of them, list order)
