@@ -309,6 +309,9 @@ int sym_rhs_get(sym_rhs r, int64_t *count, int32_t *cols_or_null);
 #define SYM_STAT_NSLEVELS 14      /* levels of the device supernodal elimination tree */
 #define SYM_STAT_NDSUPER 15       /* device supernodes (after amalgamation) */
 #define SYM_STAT_STORED_LOWER 16  /* lower-trapezoid entries stored (nnz(L) plus explicit zeros) */
+#define SYM_STAT_WALKERS 18        /* backward-sweep walkers: the (at most 64) device supernodes of
+                                     three or more blocks with the most blocks, whose diagonal chain
+                                     one workgroup walks; used while value sets x walkers <= 128 */
 #define SYM_STAT_EXT_OPERAND_ENTRIES 17 /* panel entries the external-update products read, without
                                            cache reuse: sum of (rows + columns) x inner dimension */
 int sym_stat(sym_handle h, int what, double *value);

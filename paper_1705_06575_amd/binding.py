@@ -32,7 +32,7 @@ GET_DTYPE = dict(perm=np.int32, parent=np.int32, colcount=np.int64, Lp=np.int64,
                  super_feat=np.float64, task_super=np.int32, variant=np.uint8)
 STAT = dict(n=1, nnzA=2, nnzL=3, flops=4, nsuper=5, nblocks=6, nlevels=7, npairs=8,
             panel_entries=9, analyze_ms=10, sum_rows=11, nphases=12, nincidences=13,
-            nslevels=14, ndsuper=15, stored_lower=16, ext_operand_entries=17)
+            nslevels=14, ndsuper=15, stored_lower=16, ext_operand_entries=17, walkers=18)
 
 
 class SymError(RuntimeError):

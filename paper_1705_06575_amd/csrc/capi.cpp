@@ -26,7 +26,8 @@ struct sym_plan {
            off_ctp = 0, off_ctg = 0, off_fpend = 0, off_bpend = 0, off_bdf = 0, off_sync = 0,
            off_vec4 = 0, off_vec5 = 0, off_vec6 = 0, off_part = 0, off_ttime = 0,
            off_parts = 0, off_pcount = 0, off_pbuf = 0, off_invb = 0, off_tbase = 0, off_tinit = 0,
-           off_tstate = 0, off_ctk = 0,
+           off_tstate = 0, off_ctk = 0, off_bwdf = 0, off_bwtp = 0, off_bwtg = 0, off_bwpd = 0,
+           off_bwss = 0, off_bwsq = 0,
            off_info = 0, off_dscale = 0, off_pfloor = 0, off_adiag = 0, off_acoord = 0,
            off_dsptr = 0, off_fss = 0, off_fsq = 0, off_bss = 0, off_bsq = 0, off_cptr = 0,
            off_chunks = 0;
@@ -128,6 +129,12 @@ void layout(sym_plan *h)
     h->off_tinit = take(sizeof(int32_t) * P.tinit.size());
     h->off_tstate = take(sizeof(int32_t) * P.tinit.size());
     h->off_ctk = take(sizeof(int32_t) * (size_t)P.nchain);
+    h->off_bwdf = take(sizeof(sym::SolveTask) * P.bw_df.size());
+    h->off_bwtp = take(sizeof(int64_t) * P.bw_tptr.size());
+    h->off_bwtg = take(sizeof(int32_t) * P.bw_tgt.size());
+    h->off_bwpd = take(sizeof(int32_t) * P.bw_pend.size());
+    h->off_bwss = take(sizeof(int32_t) * P.bw_slots.start.size());
+    h->off_bwsq = take(P.bw_slots.quad.size());
     h->ws_bytes = o;
 }
 
@@ -285,6 +292,12 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.tinit = (int32_t *)(base + h->off_tinit);
     D.tstate = (int32_t *)(base + h->off_tstate);
     D.cticket = (int32_t *)(base + h->off_ctk);
+    D.bw_df = (sym::SolveTask *)(base + h->off_bwdf);
+    D.bw_tptr = (int64_t *)(base + h->off_bwtp);
+    D.bw_tgt = (int32_t *)(base + h->off_bwtg);
+    D.bw_pend = (int32_t *)(base + h->off_bwpd);
+    D.bw_slot_start = (int32_t *)(base + h->off_bwss);
+    D.bw_slot_quad = (uint8_t *)(base + h->off_bwsq);
     const bool sc = sym::prec_scaled(P.precision);
     D.dscale = sc ? (double *)(base + h->off_dscale) : nullptr;
     D.pfloor = sc ? (double *)(base + h->off_pfloor) : nullptr;
@@ -302,6 +315,13 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.bwd_slot_quad, P.bwd_slots.quad.data(), P.bwd_slots.quad.size(), s);
     if (e == hipSuccess) e = upload(D.tbase, P.tbase.data(), sizeof(int32_t) * P.tbase.size(), s);
     if (e == hipSuccess) e = upload(D.tinit, P.tinit.data(), sizeof(int32_t) * P.tinit.size(), s);
+    if (e == hipSuccess) e = upload(D.bw_df, P.bw_df.data(), sizeof(sym::SolveTask) * P.bw_df.size(), s);
+    if (e == hipSuccess) e = upload(D.bw_tptr, P.bw_tptr.data(), sizeof(int64_t) * P.bw_tptr.size(), s);
+    if (e == hipSuccess) e = upload(D.bw_tgt, P.bw_tgt.data(), sizeof(int32_t) * P.bw_tgt.size(), s);
+    if (e == hipSuccess) e = upload(D.bw_pend, P.bw_pend.data(), sizeof(int32_t) * P.bw_pend.size(), s);
+    if (e == hipSuccess)
+        e = upload(D.bw_slot_start, P.bw_slots.start.data(), sizeof(int32_t) * P.bw_slots.start.size(), s);
+    if (e == hipSuccess) e = upload(D.bw_slot_quad, P.bw_slots.quad.data(), P.bw_slots.quad.size(), s);
     if (sc && e == hipSuccess) {
         e = upload(D.adiag, P.adiag.data(), sizeof(int64_t) * P.adiag.size(), s);
         if (e == hipSuccess) e = upload(D.acoord, P.acoord.data(), sizeof(int32_t) * P.acoord.size(), s);
@@ -857,6 +877,7 @@ int sym_stat(sym_handle h, int what, double *v)
     case SYM_STAT_NSLEVELS: *v = P.nslevels; break;
     case SYM_STAT_NDSUPER: *v = P.nds; break;
     case SYM_STAT_EXT_OPERAND_ENTRIES: *v = P.ext_operand_entries; break;
+    case SYM_STAT_WALKERS: *v = P.nwalk; break;
     case SYM_STAT_STORED_LOWER: {
         double st = 0;
         for (int32_t r = 0; r < P.nds; ++r) {

@@ -58,6 +58,12 @@ struct DevicePlan {
     int32_t *fwd_pend = nullptr;    // nb: initial counters of the forward sweep
     int32_t *bwd_pend = nullptr;    // nb: initial counters of the backward sweep
     SolveTask *bwd_df = nullptr;    // backward tasks in ticket order
+    SolveTask *bw_df = nullptr;     // the same with walkers (Plan::bw_df)
+    int64_t *bw_tptr = nullptr;
+    int32_t *bw_tgt = nullptr;
+    int32_t *bw_pend = nullptr;
+    int32_t *bw_slot_start = nullptr;
+    uint8_t *bw_slot_quad = nullptr;
     int32_t *pend = nullptr;        // nb: live counters
     int32_t *done = nullptr;        // nb: blocks whose backward solve is final
     int32_t *ticket = nullptr;      // next task of a running sweep

@@ -182,6 +182,12 @@ constexpr int64_t kWideLevel = 2048;   // tasks that make a level wide
 constexpr int32_t kWaveCols = 16;      // widest block of a wavefront task
 constexpr int32_t kWaveRows = 64;      // most rows below a wavefront task's block
 
+constexpr int32_t kWalkTask = -2;      // SolveTask::chunk of a backward walker
+// walkers hold workgroups while they wait for chunk tasks of later tickets:
+// the walker schedule runs only while value sets x walkers stays within this
+constexpr int32_t kWalkBudget = 128;
+constexpr int32_t kWalkMax = 64;        // walkers of a plan: the supernodes with the most blocks
+
 struct SolveTask {      // 16 bytes: one chunk of one block in a sweep
     int32_t J;
     int32_t chunk;      // rows [w + chunk*kSolveChunk, ...) below the diagonal;
@@ -249,6 +255,18 @@ struct Plan {
     std::vector<int32_t> bwd_pend;      // nb: off-diagonal chunks of the block
     std::vector<SolveTask> bwd_df;      // backward tasks, levels from the top: gathers (the last of a block finishes it), then blocks without rows below
     SweepSlots fwd_slots, bwd_slots;    // ticket slots of the two dense sweeps
+    // the backward sweep with walkers (used for few value sets): one task
+    // per wide supernode (chunk kWalkTask, J = the block it starts at, c0 =
+    // the block it ends at) finishes its blocks but the last, from the top,
+    // and computes their rows that hold the next block's columns itself;
+    // the chunk tasks of those blocks skip those rows (c0 = their count) and
+    // never finish the block (its counter starts one above their number)
+    std::vector<SolveTask> bw_df;
+    std::vector<int64_t> bw_tptr;       // bw_df chunks' target-block lists
+    std::vector<int32_t> bw_tgt;
+    std::vector<int32_t> bw_pend;       // nb
+    SweepSlots bw_slots;
+    int32_t nwalk = 0;                  // walker tasks
 
     // split external tiles: part descriptors, and the counts of arrival
     // counters and of 64 x 64 partial-tile slots they use

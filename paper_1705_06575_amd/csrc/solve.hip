@@ -31,6 +31,10 @@
 //   L_offdiag^T x from J's entries (atomics) and decrement J's counter; the
 //   chunk that empties the counter applies L_JJ^{-T} and marks J final (a
 //   block without rows below its columns has a task of its own for that).
+//   For one or two value sets, the widest supernodes' blocks are finished
+//   by a walker instead: one workgroup walks the supernode's diagonal
+//   blocks from the top and computes each block's rows that hold the next
+//   block's columns itself, with that block's solution still in LDS.
 // A task only waits for tasks with smaller tickets, which running
 // workgroups hold, so the launch always drains; a wait that exceeds its
 // bound (a corrupt plan) records an error and ends the launch.  Counters
@@ -502,6 +506,125 @@ __device__ __forceinline__ bool wave_bwd_task(const SolveTask &tk, const BlockDe
     return true;
 }
 
+// Spin until *p <= v; false, with the error word set, if the bound runs out.
+__device__ __forceinline__ bool wait_at_most(int32_t *p, int32_t v, int32_t *err)
+{
+    int it = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > v) {
+        if (++it > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+// Backward walker of one wide supernode (the whole workgroup): blocks b =
+// tk.J down to tk.c0, each followed by block b + 1.  Block b's rows that
+// hold block b + 1's columns are the walker's, with x of block b + 1 kept
+// in LDS (xs) from the step before (the first step reads it once block
+// b + 1 is final); the chunk tasks of its other rows add their sums to x_b
+// by atomics and decrement b's counter, which starts one above their
+// number.  Once it is down to one: x_b = L_bb^{-T} (x_b - the chunks' sums
+// - L_{b+1,b}^T x_{b+1}), stored, and b is marked final.  The rows' L
+// values and the diagonal inverse are fetched before the wait.  False if
+// a wait ran out.
+template <typename T>
+struct WalkStage {
+    double dv[16];      // this thread's entries of the block's staged inverse
+    T lv[16];           // its L values of the next block's rows
+};
+
+// The loads of walk step b into registers (issued before they are needed).
+template <typename T>
+__device__ __forceinline__ void walk_fetch(WalkStage<T> &st, const BlockDesc &J, int wn, const T *L)
+{
+    const int i = threadIdx.x & 63, cq = threadIdx.x >> 6;
+    const int w = J.w;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = cq + 4 * u;
+        const bool ok = i < w && c < w && i <= c;
+        const T val = L[ok ? (int64_t)c * J.ld + i : 0];
+        st.dv[u] = ok ? (double)val : 0.0;
+    }
+    const int kc = min(i, w - 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) st.lv[u] = L[(int64_t)kc * J.ld + w + min(16 * cq + u, wn - 1)];
+}
+
+// Backward walker of one wide supernode (the whole workgroup): blocks b =
+// tk.J down to tk.c0, each followed by block b + 1.  Block b's rows that
+// hold block b + 1's columns are the walker's, with x of block b + 1 kept
+// in LDS (xs) from the step before (the first step reads it once block
+// b + 1 is final); the chunk tasks of its other rows add their sums to x_b
+// by atomics and decrement b's counter, which starts one above their
+// number.  Once it is down to one: x_b = L_bb^{-T} (x_b - the chunks' sums
+// - L_{b+1,b}^T x_{b+1}), stored, and b is marked final.  The next step's
+// L values and diagonal inverse are fetched into registers while this
+// step waits and finishes.  False if a wait ran out.
+template <typename T>
+__device__ bool bwd_walk(const SolveTask &tk, const BlockDesc *__restrict__ blk,
+                         const T *__restrict__ Lx, int32_t *pend, int32_t *done, double *x,
+                         int32_t *err, double *D, double *vb, double *pp, double *xs, int *s_flag)
+{
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+    const BlockDesc Jn = blk[tk.J + 1];
+    WalkStage<T> st;
+    BlockDesc J = blk[tk.J];
+    walk_fetch(st, J, Jn.w, Lx + J.valoff);
+    if (tid == 0) *s_flag = wait_set(&done[tk.J + 1], err);
+    __syncthreads();
+    if (!*s_flag) return false;
+    if (tid < 64) xs[tid] = tid < Jn.w ? coherent_load(&x[Jn.col0 + tid]) : 0.0;
+    int wn = Jn.w;
+    for (int32_t b = tk.J; b >= tk.c0; --b) {
+        __syncthreads();                    // xs is written; the last step's LDS reads are done
+        const int w = J.w;
+        // stage the inverse (as stage_inv) and form this thread's part of
+        // L_{b+1,b}^T x_{b+1}: column lane, rows 16q .. 16q+15 of block b + 1
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = q + 4 * u;
+            if (lane < w && c < w) D[c * LDT + lane] = st.dv[u];
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = 16 * q + u;
+            s = fma(i < wn ? (double)st.lv[u] : 0.0, xs[i], s);
+        }
+        pp[q * 64 + lane] = lane < w ? s : 0.0;
+        const int32_t colb = J.col0;
+        if (b > tk.c0) {
+            const BlockDesc Jp = blk[b - 1];
+            walk_fetch(st, Jp, w, Lx + Jp.valoff);      // the next step's loads, in flight
+            J = Jp;
+        }
+        if (tid == 0) *s_flag = wait_at_most(&pend[b], 1, err);
+        __syncthreads();
+        if (!*s_flag) return false;
+        if (tid < 64)
+            vb[tid] = tid < w ? coherent_load(&x[colb + tid]) -
+                                    ((pp[tid] + pp[64 + tid]) + (pp[128 + tid] + pp[192 + tid]))
+                              : 0.0;
+        __syncthreads();
+        const double rd = (tid < 64 && tid < w) ? 1.0 / D[tid * LDT + tid] : 1.0;
+        inv_partials(D, vb, pp, 0, w, true);
+        __syncthreads();
+        if (tid < 64) {
+            const double v = rd * vb[tid] + ((pp[tid] + pp[64 + tid]) + (pp[128 + tid] + pp[192 + tid]));
+            if (tid < w) coherent_store(&x[colb + tid], v);
+            xs[tid] = tid < w ? v : 0.0;
+        }
+        complete_then_sync();
+        if (tid == 0) __hip_atomic_store(&done[b], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wn = w;
+    }
+    return true;
+}
+
 // Backward sweep, one persistent launch over the tasks in ticket order
 // (levels from the top; per level the off-diagonal chunks, then the
 // diagonal solves).  x holds y on entry and the solution on exit.
@@ -519,7 +642,7 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
                                                int32_t nb, int64_t lx_stride)
 {
     __shared__ double D[64 * LDT];
-    __shared__ double vb[64], pp[256];
+    __shared__ double vb[64], pp[256], xs[64];
     __shared__ int s_t, s_abort, s_last;
     const int tid = threadIdx.x;
     // instance blockIdx.y of a batch
@@ -550,6 +673,12 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
         for (int64_t t = ta; t < tb; ++t) {
         __syncthreads();                    // the previous task's LDS reads are done
         const SolveTask tk = tasks[t];
+        if (tk.chunk == kWalkTask) {
+            if (!bwd_walk(tk, blk, Lx, pend, done, x, err, D, vb, pp, xs, &s_last) && tid == 0) s_abort = 1;
+            __syncthreads();
+            if (s_abort) break;
+            continue;
+        }
         const BlockDesc J = blk[tk.J];
         const T *L = Lx + J.valoff;
         const int64_t ld = J.ld;
@@ -561,7 +690,7 @@ __global__ __launch_bounds__(NT, 2) void k_bwd_df(const SolveTask *__restrict__ 
             // subtract sum_{i in chunk} L_ik x[row_i] from x[J's column k]:
             // wavefront v takes columns v, v + 4, ..., lanes take rows; the
             // factor values are fetched before the wait
-            const int i0 = w + tk.chunk * NT;
+            const int i0 = w + tk.c0 + tk.chunk * NT;     // c0: rows a walker takes
             const int i1 = min(J.r, i0 + NT);
             const int32_t *rJ = rows + J.rowoff;
             int32_t ri[4];
@@ -685,12 +814,17 @@ hipError_t fwd_impl(const Plan &P, const DevicePlan &D, const SolveTask *tasks, 
 template <typename T>
 hipError_t bwd_impl(const Plan &P, const DevicePlan &D, double *y, hipStream_t s)
 {
-    const int64_t nslots = P.bwd_slots.count();
+    // walkers for few value sets (each holds a workgroup while it waits)
+    const bool walk = P.nwalk > 0 && (int64_t)D.m * P.nwalk <= kWalkBudget;
+    const int64_t nslots = walk ? P.bw_slots.count() : P.bwd_slots.count();
     if (nslots == 0) return hipGetLastError();
     const unsigned m = (unsigned)D.m;
-    k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, D.bwd_pend, D.done, P.nb, D.ticket);
+    k_sync_reset<<<dim3(grid_for(P.nb), m), 256, 0, s>>>(D.pend, walk ? D.bw_pend : D.bwd_pend, D.done, P.nb,
+                                                         D.ticket);
     k_bwd_df<T><<<dim3(sweep_grid(nslots, D.m), m), NT, 0, s>>>(
-        D.bwd_df, D.bwd_slot_start, D.bwd_slot_quad, (int)nslots, D.chunk_tptr, D.chunk_tgt, D.pend,
+        walk ? D.bw_df : D.bwd_df, walk ? D.bw_slot_start : D.bwd_slot_start,
+        walk ? D.bw_slot_quad : D.bwd_slot_quad, (int)nslots, walk ? D.bw_tptr : D.chunk_tptr,
+        walk ? D.bw_tgt : D.chunk_tgt, D.pend,
         D.done, D.ticket, D.info + 2, D.blk, D.rows, (const T *)D.Lx, y, P.n, P.nb, P.panel_entries);
     return hipGetLastError();
 }

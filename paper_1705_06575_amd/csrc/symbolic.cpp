@@ -943,6 +943,73 @@ int analyze(int64_t n64, const int64_t *Ap, const int32_t *Ai, int ordering,
     P.fwd_slots = sweep_slots(P, P.fwd_tasks, true);
     P.bwd_slots = sweep_slots(P, P.bwd_df, false);
 
+    // backward sweep with walkers: device supernodes of three or more
+    // blocks, none but the last a one-wavefront block
+    {
+        std::vector<int32_t> walk_end((size_t)nb, -1);   // at the walk's first block: its last
+        std::vector<uint8_t> walked((size_t)nb, 0);
+        std::vector<std::pair<int32_t, int32_t>> cand;    // (blocks, supernode)
+        for (int32_t r = 0; r < P.nds; ++r) {
+            if (P.dsptr[r + 1] <= P.dsptr[r]) continue;
+            const int32_t b0 = P.col2blk[P.dsptr[r]], bl = P.col2blk[P.dsptr[r + 1] - 1];
+            if (bl - b0 < 2) continue;
+            bool ok = true;
+            for (int32_t b = b0; b < bl; ++b) ok = ok && !wave_task_block(P.blk[b]);
+            if (ok) cand.push_back({bl - b0 + 1, r});
+        }
+        // the longest chains, at most kWalkMax of them
+        std::stable_sort(cand.begin(), cand.end(),
+                         [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
+                             return x.first > y.first;
+                         });
+        if ((int32_t)cand.size() > kWalkMax) cand.resize(kWalkMax);
+        P.nwalk = (int32_t)cand.size();
+        for (const auto &c : cand) {
+            const int32_t b0 = P.col2blk[P.dsptr[c.second]], bl = P.col2blk[P.dsptr[c.second + 1] - 1];
+            walk_end[bl - 1] = b0;
+            for (int32_t b = b0; b < bl; ++b) walked[b] = 1;
+        }
+        std::vector<int32_t> nchw((size_t)nb, 0), skip((size_t)nb, 0);
+        for (int32_t b = 0; b < nb; ++b) {
+            skip[b] = walked[b] ? P.blk[b + 1].w : 0;
+            nchw[b] = (P.blk[b].r - P.blk[b].w - skip[b] + kSolveChunk - 1) / kSolveChunk;
+        }
+        P.bw_df.clear();
+        P.bw_tptr.assign(1, 0);
+        P.bw_tgt.clear();
+        P.bw_pend.assign((size_t)nb, 0);
+        for (int32_t l = P.nlevels - 1; l >= 0; --l) {
+            for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+                const int32_t b = P.level_blocks[q];
+                if (walk_end[b] >= 0) P.bw_df.push_back(SolveTask{b, kWalkTask, walk_end[b], -1});
+            }
+            for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+                const int32_t b = P.level_blocks[q];
+                const BlockDesc &d = P.blk[b];
+                P.bw_pend[b] = nchw[b] + (walked[b] ? 1 : 0);
+                for (int32_t c = 0; c < nchw[b]; ++c) {
+                    const int32_t i0 = d.w + skip[b] + c * kSolveChunk, i1 = std::min(d.r, i0 + kSolveChunk);
+                    const int32_t list = (int32_t)P.bw_tptr.size() - 1;
+                    int32_t last = -1;
+                    for (int32_t i = i0; i < i1; ++i) {
+                        const int32_t b2 = P.col2blk[P.dsrows[d.rowoff + i]];
+                        if (b2 != last) {
+                            P.bw_tgt.push_back(b2);
+                            last = b2;
+                        }
+                    }
+                    P.bw_tptr.push_back((int64_t)P.bw_tgt.size());
+                    P.bw_df.push_back(SolveTask{b, c, skip[b], list});
+                }
+            }
+            for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+                const int32_t b = P.level_blocks[q];
+                if (!walked[b] && nchw[b] == 0) P.bw_df.push_back(SolveTask{b, -1, 0, -1});
+            }
+        }
+        P.bw_slots = sweep_slots(P, P.bw_df, false);
+    }
+
     // ------------------------------------------ descendant pairs (prune set)
     // Block K's rows below its own columns fall into runs of consecutive
     // local rows that lie in one target block's columns.
@@ -1127,12 +1194,16 @@ SweepSlots sweep_slots(const Plan &P, const std::vector<SolveTask> &tasks, bool 
     S.start.push_back(0);
     while (i < n) {
         int64_t j = i;
-        if (wave(i)) {
+        if (tasks[i].chunk == kWalkTask) {
+            // a walker takes a workgroup for a whole supernode: alone
+            j = i + 1;
+            S.quad.push_back(0);
+        } else if (wave(i)) {
             while (j < n && j - i < 4 && wave(j)) ++j;
             S.quad.push_back(1);
         } else {
             const int64_t cap = (i >= wa && i < wb) ? kSlotGroup : 1;
-            while (j < n && j - i < cap && !wave(j)) ++j;
+            while (j < n && j - i < cap && !wave(j) && tasks[j].chunk != kWalkTask) ++j;
             S.quad.push_back(0);
         }
         S.start.push_back((int32_t)j);

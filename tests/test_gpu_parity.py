@@ -287,6 +287,36 @@ def test_chain_launch_matches_step_launches(S, orc, torch_cuda, prec, B):
         assert np.linalg.norm(out[True][0] - f["Lx"]) <= 1e-12 * np.linalg.norm(f["Lx"])
 
 
+def test_backward_walkers_match_standard_schedule(S, orc, torch_cuda):
+    """The backward sweep with walkers (one value set: the widest
+    supernodes' diagonal chains walked by one workgroup each) and the
+    standard schedule (a batch of value sets x walkers > 128) give the same
+    solution to rounding, and the oracle's."""
+    torch = torch_cuda
+    w = W.config2(24)
+    an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm)
+    nwalk = int(an.stat("walkers"))
+    assert nwalk > 0
+    Ax = torch.from_numpy(w.Ax).cuda()
+    an.factor(Ax)
+    b = W.dense_rhs(w.n, np.random.default_rng(12))
+    x1 = an.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    m = 128 // nwalk + 1
+    bt = S.Batch(an, m)
+    bt.factor(Ax.repeat(m, 1).contiguous())
+    xb = bt.solve_(torch.from_numpy(np.tile(b, (m, 1))).cuda()).cpu().numpy()
+    bt.close()
+    f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+    x_ref = orc.solve(w.n, w.perm, f["Lp"], f["Li"], f["Lx"], b)
+    d = np.linalg.norm(x1 - xb[m - 1]) / np.linalg.norm(xb[m - 1])
+    e = np.linalg.norm(x1 - x_ref) / np.linalg.norm(x_ref)
+    eta = orc.eta_inf(w.n, w.Ap, w.Ai, w.Ax, x1, b)
+    _say(f"case walkers: {nwalk} walkers, batch of {m} on the standard schedule; rel diff {d:.1e}, "
+         f"vs oracle {e:.1e}, eta {eta:.1e}")
+    # same factor; the sweeps' atomic sums differ in order only
+    assert d <= 1e-10 and e <= 1e-9 and eta <= 1e-14
+
+
 @pytest.mark.parametrize("m", [12, 24])
 def test_grid3d_scaled(S, orc, torch_cuda, m):
     w = W.config2(m)
