@@ -100,7 +100,13 @@ typedef struct sym_opts {
                                 launch per step and kind; 1: as one persistent launch per level
                                 whose tasks wait for the tiles they read (same results, bit for
                                 bit; measured slower on this chip, kept for comparison) */
-    int32_t reserved[3];
+    int32_t update_depth;    /* step launches (chain_launch 0): the updates of a supernode's later
+                                blocks by its column blocks are applied in groups of this many
+                                consecutive blocks, as one product per target tile with an inner
+                                dimension of up to update_depth x block_width; inside a group each
+                                block updates only the group's later blocks (0 = 4; 1 = one block
+                                at a time; at most 16).  Same factor up to rounding order. */
+    int32_t reserved[2];
 } sym_opts;
 
 typedef struct sym_plan *sym_handle;

@@ -53,7 +53,8 @@ class sym_opts(ctypes.Structure):
                 ("max_super_width", ctypes.c_int32),
                 ("split_share", ctypes.c_int32),
                 ("chain_launch", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("update_depth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 EXPORTS = ["sym_opts_default", "sym_analyze", "sym_workspace", "sym_bind", "sym_factor",
@@ -192,7 +193,7 @@ class Analysis:
 
     def __init__(self, n, Ap, Ai, ordering="nd", block_width=64, precision="f64", nd_leaf=24,
                  amalgamate=True, pivot_floor_exp=0, max_super_width=0, split_share=0,
-                 chain_launch=False):
+                 chain_launch=False, update_depth=0):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -217,6 +218,7 @@ class Analysis:
         o.max_super_width = int(max_super_width)
         o.split_share = int(split_share)
         o.chain_launch = int(bool(chain_launch))
+        o.update_depth = int(update_depth)
         o.nd_leaf = int(nd_leaf)
         o.amalgamate = int(bool(amalgamate))
         self.precision = precision
@@ -253,7 +255,7 @@ class Analysis:
         return v.value
 
     def set_variants(self, variant):
-        """Per-device-supernode kernel variants (0..2); the analysis is
+        """Per-device-supernode kernel variants (0..3); the analysis is
         unbound afterwards and binds again on its next device call."""
         v = np.ascontiguousarray(variant, dtype=np.uint8)
         _check("sym_set_variants", self._lib.sym_set_variants(self._h, _ptr(v), int(v.size)))

@@ -192,6 +192,7 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
     if (o.pivot_floor_exp < -60 || o.pivot_floor_exp > 1) return SYM_EINVAL;
     if (o.split_share < 0 || o.split_share > (1 << 24)) return SYM_EINVAL;
     if (o.chain_launch != 0 && o.chain_launch != 1) return SYM_EINVAL;
+    if (o.update_depth < 0 || o.update_depth > sym::kMaxUpdateDepth) return SYM_EINVAL;
     sym_plan *h = new (std::nothrow) sym_plan();
     if (!h) return SYM_ENOMEM;
     int rc;
@@ -199,6 +200,7 @@ int sym_analyze(int64_t n, const int64_t *Ap, const int32_t *Ai, const sym_opts 
         h->P.precision = o.precision;
         if (o.split_share > 0) h->P.split_share = o.split_share;
         h->P.chain_launch = o.chain_launch != 0;
+        if (o.update_depth > 0) h->P.update_depth = o.update_depth;
         // pivot floor of the scaled precisions: 2^exp, the default by format
         // (SYM_PIVOT_FLOOR_DEFAULT_*), or none (exp = 1)
         if (sym::prec_scaled(o.precision) && o.pivot_floor_exp != 1) {

@@ -1376,10 +1376,13 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
 }
 
 // Internal (right-looking) update of one row tile of block J by the final
-// block K of the same supernode: tile -= L_K[tile rows, :] L_K[J's columns, :]^T.
-// J's local row 0 is K's local row d = col0_J - col0_K, so no index lookups
-// are needed.  The accumulators start from the tile's current values.  With
-// kFuseFactor (tile 0 of block K+1) the result is factored in LDS.
+// blocks K, ..., K + g - 1 of the same supernode (g from the task's flags):
+// tile -= sum_k L_k[tile rows, :] L_k[J's columns, :]^T, one accumulation
+// over all g blocks' columns, so each entry takes the same sequence of
+// products as with one block per step.  J's local row 0 is block k's local
+// row d = col0_J - col0_k, so no index lookups are needed.  The
+// accumulators start from the tile's current values.  With kFuseFactor
+// (tile 0 of the block after the last source) the result is factored in LDS.
 template <typename T, int OP>
 __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tasks,
                                                  const BlockDesc *__restrict__ blk,
@@ -1397,13 +1400,10 @@ __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tas
     const int wr = wave >> 1, wc = wave & 1;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc J = blk[tk.J];
-    const BlockDesc K = blk[tk.K];
-    const int d = J.col0 - K.col0;
     const int r0 = tk.t * TR;
     const int nr = min(TR, J.r - r0);
     const int w = J.w;
     T *LJ = Lx + J.valoff;
-    const T *LK = Lx + K.valoff;
     const bool active = 32 * wr < nr && 32 * wc < w;
 
     typename Mfma<T>::acc_t acc[2][2] = {};
@@ -1425,7 +1425,12 @@ __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tas
                     const T val = *reinterpret_cast<const T *>(tb + off);
                     acc[m][n][v] = ok ? val : T(0);
                 }
-        wave_product_pipe<T, OP>(LK + d + r0, LK + d, K.ld, nr, w, K.w, wr, wc, acc);
+        const int32_t k1 = tk.K + (tk.flags >> kDepthShift);
+        for (int32_t k = tk.K; k <= k1; ++k) {
+            const BlockDesc K = blk[k];
+            const T *LK = Lx + K.valoff + (J.col0 - K.col0);
+            wave_product_pipe<T, OP>(LK + r0, LK, K.ld, nr, w, K.w, wr, wc, acc);
+        }
     }
     if (tk.flags & kFuseFactor) {
         if (active) {

@@ -39,7 +39,8 @@ struct Task {           // 16 bytes: one row tile of one block
     int32_t J;          // target block
     int32_t t;          // tile index: local rows [t*T, min((t+1)*T, r_J))
     int32_t K;          // source block (internal updates), PartDesc index (kPartial), else -1
-    int32_t flags;      // kFuseFactor: the task also factors the block
+    int32_t flags;      // kFuseFactor: the task also factors the block; internal
+                        // updates: source block count - 1 from bit kDepthShift
 };
 
 // One descendant block K's contribution to one row tile of a target block
@@ -101,6 +102,12 @@ static_assert(sizeof(WaveItem) == 32, "WaveItem layout is shared with the device
 static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
 constexpr int32_t kFuseFactor = 1;
+// An internal update (kPhaseInternal) reads the source blocks K, K + 1, ...,
+// K + (flags >> kDepthShift) of the target's supernode, one product of inner
+// dimension up to kMaxUpdateDepth x 64 per tile (Plan::update_depth).
+constexpr int32_t kDepthShift = 8;
+constexpr int32_t kUpdateDepth = 4;
+constexpr int32_t kMaxUpdateDepth = 16;
 // A task of a chain launch (kPhaseChain) that ends by solving its tile
 // against its block's factored diagonal block (X := X L_JJ^{-T}).
 constexpr int32_t kChainSolve = 8;
@@ -206,6 +213,7 @@ struct Plan {
     double pivot_floor = 0.0;   // tau: pivots below tau times their scaled diagonal entry are
                                 // replaced by it (scaled precisions only; 0 = never)
     bool chain_launch = false;  // the steps inside a level's supernodes as one persistent launch
+    int32_t update_depth = kUpdateDepth;  // source blocks per grouped internal update
     double analyze_ms = 0.0;
 
     // ---- ordering and column structure (permuted numbering)

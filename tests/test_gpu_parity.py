@@ -287,6 +287,30 @@ def test_chain_launch_matches_step_launches(S, orc, torch_cuda, prec, B):
         assert np.linalg.norm(out[True][0] - f["Lx"]) <= 1e-12 * np.linalg.norm(f["Lx"])
 
 
+@pytest.mark.parametrize("prec,B", [("f64", 64), ("f32", 64), ("bf16", 64), ("f64", 32)])
+def test_update_depth_same_factor(S, orc, torch_cuda, prec, B):
+    """Grouping a supernode's internal updates (one product over up to 16
+    source blocks per target tile) keeps each entry's accumulation sequence,
+    so the factor is bit for bit that of one block at a time; the FP64
+    factor equals the oracle."""
+    torch = torch_cuda
+    w = W.config2(24)
+    Ax = torch.from_numpy(w.Ax).cuda()
+    out = {}
+    for depth in (1, 2, 4, 16):
+        an = S.Analysis(w.n, w.Ap, w.Ai, ordering=w.perm, precision=prec, block_width=B, update_depth=depth)
+        an.factor(Ax)
+        assert an.status() == 0
+        out[depth] = an.export_factor()
+        an.close()
+    _say(f"case update depth {prec} B{B}: {len(out)} depths")
+    for depth in (2, 4, 16):
+        assert np.array_equal(out[depth].view(np.uint64), out[1].view(np.uint64))
+    if prec == "f64":
+        f = orc.factor(w.n, w.Ap, w.Ai, w.Ax, w.perm)
+        assert np.linalg.norm(out[4] - f["Lx"]) <= 1e-12 * np.linalg.norm(f["Lx"])
+
+
 def test_backward_walkers_match_standard_schedule(S, orc, torch_cuda):
     """The backward sweep with walkers (one value set: the widest
     supernodes' diagonal chains walked by one workgroup each) and the

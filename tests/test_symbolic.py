@@ -264,6 +264,21 @@ def test_chain_launch_schedule(S):
             assert c.kind_flops() == a.kind_flops()
 
 
+def test_update_depth_option(S):
+    """update_depth groups the internal updates inside a supernode; the
+    launch count and the method's flops do not depend on it, and values
+    outside 0..16 are rejected."""
+    w = W.config2(20)
+    ref = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", update_depth=1)
+    for depth in (0, 2, 4, 16):
+        a = S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", update_depth=depth)
+        assert a.stat("nphases") == ref.stat("nphases")
+        assert a.stat("flops") == ref.stat("flops")
+    for bad in (-1, 17):
+        with pytest.raises(RuntimeError):
+            S.Analysis(w.n, w.Ap, w.Ai, ordering="nd", update_depth=bad)
+
+
 def test_supernode_features(S):
     """The cost model's features: sizes match the device supernodes, the
     update flops (whole tile products, so at least the external-update
