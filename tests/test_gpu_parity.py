@@ -419,3 +419,10 @@ def test_config2_full_size_invariants(S, orc, torch_cuda):
     rs = _rel(orc.lmul(w.n, Lp, Li, Lx, ys), bb)
     _say(f"  sparse forward residual {rs:.3e} reach {reach.size}/{w.n}")
     assert rs <= 1e-13
+    # element by element against the oracle's pruned substitution over the
+    # same reach with the same factor (summation order differs only)
+    y_ref = orc.fwd_pruned(w.n, Lp, Li, Lx, reach, bb)
+    es = _rel(ys, y_ref)
+    _say(f"  sparse forward vs oracle's pruned substitution {es:.3e}")
+    assert es <= 1e-13
+    assert (y_ref[outside] == 0.0).all()
