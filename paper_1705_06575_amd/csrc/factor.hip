@@ -1462,6 +1462,34 @@ __global__ __launch_bounds__(NT, 3) void k_internal(const Task *__restrict__ tas
     }
 }
 
+// Leaves of the supernodal tree whose block is a single tile of at most 16
+// columns: no update reaches them, so the block is only factored, one
+// wavefront per block, with the fused-tile path's steps (the values as
+// stored, widened to FP64, the same pivot steps, rounded once on the way
+// out), so the factor is the same bit for bit.
+template <typename T, bool FLOOR>
+__global__ __launch_bounds__(64) void k_leaf(const Task *__restrict__ tasks, const BlockDesc *__restrict__ blk,
+                                             T *__restrict__ Lx, int32_t *__restrict__ info, int64_t lx_stride,
+                                             const double *__restrict__ pfloor, int32_t n)
+{
+    Lx += blockIdx.y * lx_stride;
+    info += 4 * blockIdx.y;
+    if (pfloor) pfloor += (int64_t)blockIdx.y * n;
+    __shared__ double C[16 * LDC];
+    const BlockDesc J = blk[tasks[blockIdx.x].J];
+    const int nr = min(J.r, 64), w = min(J.w, 16);
+    T *LJ = Lx + J.valoff;
+    const int i = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) C[c * LDC + i] = (i < nr && c < w) ? (double)LJ[(int64_t)c * J.ld + i] : 0.0;
+    __syncthreads();
+    wave_subpanel<double, FLOOR>(C, 0, w, nr, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (i < nr && c < w) LJ[(int64_t)c * J.ld + i] = (T)C[c * LDC + i];
+}
+
 // Row tile t >= 1 of block J solves X := X L_JJ^{-T} against J's factored
 // diagonal block, blocked by 16 columns: the four wavefronts first invert
 // one 16 x 16 diagonal triangle each, then each solves 16 of the tile's rows
@@ -1861,7 +1889,7 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
     int32_t chain = 0;
     for (const Phase &ph : P.phases) {
         const dim3 g((unsigned)(ph.t1 - ph.t0), m);
-        Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
+        Bracket b(prof, s, (ph.kind == kPhaseExternal || ph.kind == kPhaseLeaf) ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
         if (ph.kind == kPhaseChain) {
             const int64_t nt = ph.t1 - ph.t0;
             const unsigned gx = (unsigned)std::min<int64_t>(nt, std::max(16, kChainGrid / (int)m));
@@ -1883,6 +1911,8 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
                                                       D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                       D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
                                                       pfloor, P.n, D.cptr + ph.t0, D.chunks);
+        else if (ph.kind == kPhaseLeaf)
+            k_leaf<T, OP != kOpNative><<<g, 64, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs, pfloor, P.n);
         else if (ph.kind == kPhaseInternal)
             k_internal<T, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs, pfloor, P.n);
         else

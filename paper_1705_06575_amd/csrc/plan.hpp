@@ -152,7 +152,11 @@ constexpr int kSuperFeatures = 12;  // features of a device supernode, see Plan:
 // launch whose tasks wait for the tiles they read (Plan::tbase; only with
 // Plan::chain_launch); by default every step is a kPhaseInternal launch
 // followed by a kPhaseTrsm launch.
-enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2, kPhaseChain = 3 };
+// A kPhaseLeaf launch factors leaves of the supernodal tree whose block is
+// one tile of at most 16 columns (no update reaches a leaf), one wavefront
+// per block.
+enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2, kPhaseChain = 3,
+                           kPhaseLeaf = 4 };
 struct Phase {
     int32_t kind;
     int64_t t0, t1;     // task range in Plan::ftasks

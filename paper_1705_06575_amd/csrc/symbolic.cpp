@@ -361,9 +361,11 @@ void build_schedule(Plan &P)
         std::vector<RawInc> incs;
     };
     std::vector<Pending> pending;
+    std::vector<int32_t> leaves;
     for (int32_t l = 0; l < P.nslevels; ++l) {
         int32_t maxnb = 0;
         pending.clear();
+        leaves.clear();
         open_phase(kPhaseExternal);
         for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
             const int32_t s2 = sl_list[q];
@@ -393,6 +395,13 @@ void build_schedule(Plan &P)
                     }
                 }
                 const bool first = J == P.sbptr[s2];
+                if (first && nt == 1 && dJ.w <= 16 && per_tile[0].empty()) {
+                    // a leaf of one narrow tile: factored by the level's
+                    // one-wavefront launch, not as an update tile
+                    leaves.push_back(J);
+                    P.sfeat[(size_t)s2 * kSuperFeatures + 2] += 1.0;
+                    continue;
+                }
                 for (int32_t t = 0; t < nt; ++t) {
                     const bool fuse = first && t == 0;
                     if (per_tile[t].empty() && !fuse) continue;
@@ -479,6 +488,11 @@ void build_schedule(Plan &P)
             }
         }
         close_phase();
+        if (!leaves.empty()) {
+            open_phase(kPhaseLeaf);
+            for (int32_t J : leaves) push_task(J, 0, -1, kFuseFactor, 0);
+            close_phase();
+        }
         if (P.chain_launch) {
             emit_chain(l);
             continue;
