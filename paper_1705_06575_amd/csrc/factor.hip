@@ -483,9 +483,8 @@ __device__ __forceinline__ float pivot_rsqrt(float d)
 // replacements goes to info[3]); a NaN pivot is never replaced.
 template <typename T, bool FLOOR>
 __device__ __forceinline__ void wave_subpanel(T *C, int c0, int wb, int nr, int col0,
-                                              int32_t *info, const double *floor)
+                                              int32_t *info, const double *floor, double *bcast)
 {
-    __shared__ double bcast[64];
     const int lane = threadIdx.x & 63;
     const int row = c0 + lane;
     const bool mine = row < nr;
@@ -652,15 +651,16 @@ template <bool FLOOR, typename T>
 __device__ __forceinline__ void panel_factor(T *C, int nr, int w, int col0, int32_t *info,
                                              const double *floor)
 {
+    __shared__ double bcast[64];        // the sub-panel's column broadcasts
     const int wave = threadIdx.x >> 6;
-    if (wave == 0) wave_subpanel<T, FLOOR>(C, 0, min(16, w), nr, col0, info, floor);
+    if (wave == 0) wave_subpanel<T, FLOOR>(C, 0, min(16, w), nr, col0, info, floor, bcast);
     __syncthreads();
     for (int c0 = 16; c0 < w; c0 += 16) {
         const int wb = min(16, w - c0);
         block_update(C, C, C, c0, nr, c0, c0 + wb, c0 - 16, 16, 0);
         __syncthreads();
         if (wave == 0)
-            wave_subpanel<T, FLOOR>(C, c0, wb, nr, col0, info, floor);
+            wave_subpanel<T, FLOOR>(C, c0, wb, nr, col0, info, floor, bcast);
         else if (c0 + wb < w)
             block_update(C, C, C, c0 + wb, nr, c0 + wb, w, c0 - 16, 16, 0, 1);
         __syncthreads();
@@ -1233,7 +1233,8 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
                                                  int32_t *pcount, T *pbuf, int32_t nsplit,
                                                  int64_t npartial, const double *__restrict__ pfloor,
                                                  int32_t n, const int64_t *__restrict__ cptr,
-                                                 const StageChunk *__restrict__ chunks)
+                                                 const StageChunk *__restrict__ chunks,
+                                                 int64_t nwide, int64_t ntasks)
 {
     const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
     // the tile, in the panels' precision; FP64-sized so that a fused
@@ -1254,6 +1255,54 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    if ((int64_t)blockIdx.x >= nwide) {
+        // four tiles of blocks of at most 16 columns, one per wavefront, in
+        // its own 16 LDS columns: the tile, its item stream (a narrow
+        // tile's products all belong to the first wavefront's columns),
+        // then with kFuseFactor the diagonal factorization in FP64; the
+        // whole-workgroup path's steps, so the same values.  No barriers.
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int64_t q = nwide + 4 * ((int64_t)blockIdx.x - nwide) + wv;
+        if (q >= ntasks) return;
+        double *Cw = Cbuf + wv * 16 * LDC;
+        T *Cn = reinterpret_cast<T *>(Cw);
+        const Task tk = tasks[q];
+        const BlockDesc J = blk[tk.J];
+        const int r0 = tk.t * TR;
+        const int nr = min(TR, J.r - r0);
+        const int w = min(J.w, 16);
+        T *LJ = Lx + J.valoff;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            Cn[c * LDC + lane] = (lane < nr && c < w) ? LJ[(int64_t)c * J.ld + r0 + lane] : T(0);
+        const int64_t *wg = wptr + 16 * q;
+        if (wg[0] < wg[1]) wave_items<T, OP, 4>(Cn, witems, wmap, (const T *)Lx, wg[0], wg[1], r0, nr, w);
+        if (wg[1] < wg[2]) wave_items<T, OP, 3>(Cn, witems, wmap, (const T *)Lx, wg[1], wg[2], r0, nr, w);
+        if (wg[2] < wg[3]) wave_items<T, OP, 2>(Cn, witems, wmap, (const T *)Lx, wg[2], wg[3], r0, nr, w);
+        if (wg[3] < wg[4]) wave_items<T, OP, 1>(Cn, witems, wmap, (const T *)Lx, wg[3], wg[4], r0, nr, w);
+        if (tk.flags & kFuseFactor) {
+            if constexpr (sizeof(T) != sizeof(double)) {
+                T v[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) v[c] = Cn[c * LDC + lane];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                for (int c = 0; c < 16; ++c) Cw[c * LDC + lane] = (double)v[c];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+            wave_subpanel<double, OP != kOpNative>(Cw, 0, w, nr, J.col0, info,
+                                                   pfloor ? pfloor + J.col0 : nullptr, stage_mem + 64 * wv);
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (lane < nr && c < w) LJ[(int64_t)c * J.ld + r0 + lane] = (T)Cw[c * LDC + lane];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (lane < nr && c < w) LJ[(int64_t)c * J.ld + r0 + lane] = Cn[c * LDC + lane];
+        }
+        if (ttime && blockIdx.y == 0 && lane == 0) ttime[q] = wall_clock64() - t_start;
+        return;
+    }
     const Task tk = tasks[blockIdx.x];
     const BlockDesc J = blk[tk.J];
     const int r0 = tk.t * TR;
@@ -1476,6 +1525,7 @@ __global__ __launch_bounds__(64) void k_leaf(const Task *__restrict__ tasks, con
     info += 4 * blockIdx.y;
     if (pfloor) pfloor += (int64_t)blockIdx.y * n;
     __shared__ double C[16 * LDC];
+    __shared__ double bcast[64];
     const BlockDesc J = blk[tasks[blockIdx.x].J];
     const int nr = min(J.r, 64), w = min(J.w, 16);
     T *LJ = Lx + J.valoff;
@@ -1483,7 +1533,7 @@ __global__ __launch_bounds__(64) void k_leaf(const Task *__restrict__ tasks, con
 #pragma unroll
     for (int c = 0; c < 16; ++c) C[c * LDC + i] = (i < nr && c < w) ? (double)LJ[(int64_t)c * J.ld + i] : 0.0;
     __syncthreads();
-    wave_subpanel<double, FLOOR>(C, 0, w, nr, J.col0, info, pfloor ? pfloor + J.col0 : nullptr);
+    wave_subpanel<double, FLOOR>(C, 0, w, nr, J.col0, info, pfloor ? pfloor + J.col0 : nullptr, bcast);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 16; ++c)
@@ -1899,18 +1949,21 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
             ++chain;
             continue;
         }
+        const int64_t nt = ph.t1 - ph.t0;
+        const int64_t nwide = ph.nwide < 0 ? nt : ph.nwide;
+        const dim3 gx((unsigned)(nwide + (nt - nwide + 3) / 4), m);
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
-            k_external<T, true, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
+            k_external<T, true, OP><<<gx, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                      D.incs, D.imap, D.wptr + 16 * ph.t0, D.witems,
                                                      D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                      D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
-                                                     pfloor, P.n, D.cptr + ph.t0, D.chunks);
+                                                     pfloor, P.n, D.cptr + ph.t0, D.chunks, nwide, nt);
         else if (ph.kind == kPhaseExternal)
-            k_external<T, false, OP><<<g, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
+            k_external<T, false, OP><<<gx, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                       D.incs, D.imap, D.wptr + 16 * ph.t0, D.witems,
                                                       D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                       D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
-                                                      pfloor, P.n, D.cptr + ph.t0, D.chunks);
+                                                      pfloor, P.n, D.cptr + ph.t0, D.chunks, nwide, nt);
         else if (ph.kind == kPhaseLeaf)
             k_leaf<T, OP != kOpNative><<<g, 64, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs, pfloor, P.n);
         else if (ph.kind == kPhaseInternal)

@@ -154,12 +154,15 @@ constexpr int kSuperFeatures = 12;  // features of a device supernode, see Plan:
 // followed by a kPhaseTrsm launch.
 // A kPhaseLeaf launch factors leaves of the supernodal tree whose block is
 // one tile of at most 16 columns (no update reaches a leaf), one wavefront
-// per block.
+// per block.  An external launch's tasks from Phase::nwide on are tiles of
+// blocks of at most 16 columns (not split, not staged), four to a
+// workgroup, one wavefront each.
 enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2, kPhaseChain = 3,
                            kPhaseLeaf = 4 };
 struct Phase {
     int32_t kind;
     int64_t t0, t1;     // task range in Plan::ftasks
+    int64_t nwide = -1; // kPhaseExternal: tasks of whole workgroups (the rest: one wavefront each); -1 = all
 };
 
 // Factor precisions (sym.h: SYM_F64, SYM_F32, SYM_BF16, SYM_F16).  FP32

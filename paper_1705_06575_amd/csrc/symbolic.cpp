@@ -425,7 +425,11 @@ void build_schedule(Plan &P)
         double lv_cost = 0.0;
         for (const Pending &pd : pending) lv_cost += pd.cost;
         const double unit = std::max(kSplitUnits, lv_cost / P.split_share);
-        for (const Pending &pd : pending) {
+        // tiles of blocks of at most 16 columns that are neither split nor
+        // staged go to the level's one-wavefront launch (their products are
+        // all per-wavefront items of the first wavefront)
+        std::vector<const Pending *> narrow;
+        auto emit_pending = [&](const Pending &pd, bool narrow_pass) {
             int32_t np = 1;
             if (pd.cost > unit)
                 np = std::min<int32_t>((int32_t)std::ceil(pd.cost / unit), (int32_t)pd.incs.size());
@@ -440,6 +444,10 @@ void build_schedule(Plan &P)
                 np = (int32_t)cut.size();
             }
             cut.push_back(pd.incs.size());
+            if (!narrow_pass && np == 1 && P.blk[pd.J].w <= 16 && P.svariant[pd.s2] != kVariantStaged) {
+                narrow.push_back(&pd);
+                return;
+            }
             const int32_t counter = np > 1 ? lv_counters++ : -1;
             const int64_t slot0 = lv_slots;
             if (np > 1) lv_slots += np;
@@ -486,7 +494,10 @@ void build_schedule(Plan &P)
                         push_task(J, t, -1, (fuse ? kFuseFactor : 0) | sflag, big_end);
                     }
             }
-        }
+        };
+        for (const Pending &pd : pending) emit_pending(pd, false);
+        P.phases.back().nwide = (int64_t)P.ftasks.size() - P.phases.back().t0;
+        for (const Pending *pd : narrow) emit_pending(*pd, true);
         close_phase();
         if (!leaves.empty()) {
             open_phase(kPhaseLeaf);
