@@ -329,7 +329,8 @@ int sym_stat(sym_handle h, int what, double *value);
  * time in ms and the launch count of each kernel kind:
  *   [0] A scatter (zero fill + placement), [1] external (descendant)
  *   updates, [2] off-diagonal triangular solves and the diagonal-block
- *   inverses, [3] internal updates.
+ *   inverses, [3] internal updates and the factorizations of leaf blocks
+ *   (single narrow tiles that no update reaches).
  * algorithmic_flops[k] is the arithmetic each kind performs by the
  * method's count (lower-triangle products only), from the analysis.
  * Arrays hold SYM_PROFILE_KINDS entries.  Errors: SYM_EINVAL, SYM_ESTATE,

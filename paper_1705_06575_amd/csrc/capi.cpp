@@ -19,7 +19,7 @@ static_assert(SYM_STATIC_MAX_N == sym::kStaticMaxN, "static scratch bound of the
 struct sym_plan {
     sym::Plan P;
     size_t ws_bytes = 0;
-    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_iptr = 0, off_ibig = 0, off_incs = 0, off_imap = 0,
+    size_t off_Lx = 0, off_blk = 0, off_rows = 0, off_tasks = 0, off_xslot = 0, off_iptr = 0, off_ibig = 0, off_incs = 0, off_imap = 0,
            off_wptr = 0, off_witems = 0, off_wmap = 0,
            off_lvl = 0, off_amap = 0, off_perm = 0, off_vec = 0, off_vec2 = 0, off_ftk = 0, off_btk = 0,
            off_vec3 = 0, off_arp = 0, off_acol = 0, off_aval = 0, off_red = 0,
@@ -78,6 +78,7 @@ void layout(sym_plan *h)
     h->off_blk = take(sizeof(sym::BlockDesc) * P.blk.size());
     h->off_rows = take(sizeof(int32_t) * P.dsrows.size());
     h->off_tasks = take(sizeof(sym::Task) * P.ftasks.size());
+    h->off_xslot = take(sizeof(int32_t) * P.xslot.size());
     h->off_iptr = take(sizeof(int64_t) * P.iptr.size());
     h->off_ibig = take(sizeof(int64_t) * P.ibig.size());
     h->off_incs = take(sizeof(sym::Incidence) * P.incs.size());
@@ -247,6 +248,7 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     D.blk = (sym::BlockDesc *)(base + h->off_blk);
     D.rows = (int32_t *)(base + h->off_rows);
     D.tasks = (sym::Task *)(base + h->off_tasks);
+    D.xslot = (int32_t *)(base + h->off_xslot);
     D.iptr = (int64_t *)(base + h->off_iptr);
     D.ibig = (int64_t *)(base + h->off_ibig);
     D.incs = (sym::Incidence *)(base + h->off_incs);
@@ -332,6 +334,7 @@ int sym_bind(sym_handle h, void *dev_ws, size_t bytes, void *stream)
     if (e == hipSuccess) e = upload(D.blk, P.blk.data(), sizeof(sym::BlockDesc) * P.blk.size(), s);
     if (e == hipSuccess) e = upload(D.rows, P.dsrows.data(), sizeof(int32_t) * P.dsrows.size(), s);
     if (e == hipSuccess) e = upload(D.tasks, P.ftasks.data(), sizeof(sym::Task) * P.ftasks.size(), s);
+    if (e == hipSuccess) e = upload(D.xslot, P.xslot.data(), sizeof(int32_t) * P.xslot.size(), s);
     if (e == hipSuccess) e = upload(D.iptr, P.iptr.data(), sizeof(int64_t) * P.iptr.size(), s);
     if (e == hipSuccess) e = upload(D.ibig, P.ibig.data(), sizeof(int64_t) * P.ibig.size(), s);
     if (e == hipSuccess) e = upload(D.incs, P.incs.data(), sizeof(sym::Incidence) * P.incs.size(), s);

@@ -21,6 +21,7 @@ struct DevicePlan {
     BlockDesc *blk = nullptr;       // nb
     int32_t *rows = nullptr;        // sum of supernode row counts
     Task *tasks = nullptr;          // factor tasks in launch order
+    int32_t *xslot = nullptr;       // external launches' workgroup slots (Plan::xslot)
     int64_t *iptr = nullptr;        // tasks+1: incidence ranges of external-update tasks
     int64_t *ibig = nullptr;        // tasks: end of each task's leading large incidences
     Incidence *incs = nullptr;      // (tile, descendant) incidences

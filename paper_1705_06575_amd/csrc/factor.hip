@@ -1234,7 +1234,7 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
                                                  int64_t npartial, const double *__restrict__ pfloor,
                                                  int32_t n, const int64_t *__restrict__ cptr,
                                                  const StageChunk *__restrict__ chunks,
-                                                 int64_t nwide, int64_t ntasks)
+                                                 const int32_t *__restrict__ xslot)
 {
     const unsigned long long t_start = ttime ? wall_clock64() : 0ull;
     // the tile, in the panels' precision; FP64-sized so that a fused
@@ -1255,15 +1255,19 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    if ((int64_t)blockIdx.x >= nwide) {
-        // four tiles of blocks of at most 16 columns, one per wavefront, in
-        // its own 16 LDS columns: the tile, its item stream (a narrow
-        // tile's products all belong to the first wavefront's columns),
-        // then with kFuseFactor the diagonal factorization in FP64; the
-        // whole-workgroup path's steps, so the same values.  No barriers.
+    // this workgroup slot's task, or its narrow tiles
+    const int32_t e0 = xslot[blockIdx.x], e1 = xslot[blockIdx.x + 1] & INT32_MAX;
+    const int32_t tq = e0 & INT32_MAX;
+    if (e0 < 0) {
+        // up to four tiles of blocks of at most 16 columns, one per
+        // wavefront, in its own 16 LDS columns: the tile, its item stream
+        // (a narrow tile's products all belong to the first wavefront's
+        // columns), then with kFuseFactor the diagonal factorization in
+        // FP64; the whole-workgroup path's steps, so the same values.  No
+        // barriers.
         const int wv = __builtin_amdgcn_readfirstlane(wave);
-        const int64_t q = nwide + 4 * ((int64_t)blockIdx.x - nwide) + wv;
-        if (q >= ntasks) return;
+        const int32_t q = tq + wv;
+        if (q >= e1) return;
         double *Cw = Cbuf + wv * 16 * LDC;
         T *Cn = reinterpret_cast<T *>(Cw);
         const Task tk = tasks[q];
@@ -1303,7 +1307,7 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
         if (ttime && blockIdx.y == 0 && lane == 0) ttime[q] = wall_clock64() - t_start;
         return;
     }
-    const Task tk = tasks[blockIdx.x];
+    const Task tk = tasks[tq];
     const BlockDesc J = blk[tk.J];
     const int r0 = tk.t * TR;
     const int nr = min(TR, J.r - r0);
@@ -1319,15 +1323,15 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     }
     __syncthreads();
 
-    int64_t q = iptr[blockIdx.x];
+    int64_t q = iptr[tq];
     if (tk.flags & kStaged) {
-        staged_products<T, OP>(C, reinterpret_cast<T(*)[kStageK][64]>(stage_mem), chunks, cptr[blockIdx.x],
-                               cptr[blockIdx.x + 1], imap, (const T *)Lx, r0, nr, w);
+        staged_products<T, OP>(C, reinterpret_cast<T(*)[kStageK][64]>(stage_mem), chunks, cptr[tq],
+                               cptr[tq + 1], imap, (const T *)Lx, r0, nr, w);
     } else if constexpr (COOP && OP == kOpNative) {
         constexpr int KC = 8;   // inner indices per staged chunk of the cooperative product
         T(*As)[KC][64] = reinterpret_cast<T(*)[KC][64]>(stage_mem);
         T(*Bs)[KC][64] = reinterpret_cast<T(*)[KC][64]>(stage_mem + KC * 64 * 2 * sizeof(T) / sizeof(double));
-        const int64_t qb = ibig[blockIdx.x];
+        const int64_t qb = ibig[tq];
         for (; q < qb; ++q) {
             const Incidence in = incs[q];
             if (in.nI > nr || in.nJ > w) {       // corrupt plan: never write outside the tile
@@ -1339,7 +1343,7 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     } else if constexpr (COOP) {
         uint64_t(*Ap)[4][64] = reinterpret_cast<uint64_t(*)[4][64]>(stage_mem);
         uint64_t(*Bp)[4][64] = reinterpret_cast<uint64_t(*)[4][64]>(stage_mem + 2 * 4 * 64);
-        const int64_t qb = ibig[blockIdx.x];
+        const int64_t qb = ibig[tq];
         for (; q < qb; ++q) {
             const Incidence in = incs[q];
             if (in.nI > nr || in.nJ > w) {
@@ -1352,7 +1356,7 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
 
     // the small incidences: each wavefront runs its own item list
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int64_t *wg = wptr + 16 * (int64_t)blockIdx.x + 4 * wv;
+    const int64_t *wg = wptr + 16 * (int64_t)tq + 4 * wv;
     if (wg[0] < wg[1]) wave_items<T, OP, 4>(C, witems, wmap, (const T *)Lx, wg[0], wg[1], r0, nr, w);
     if (wg[1] < wg[2]) wave_items<T, OP, 3>(C, witems, wmap, (const T *)Lx, wg[1], wg[2], r0, nr, w);
     if (wg[2] < wg[3]) wave_items<T, OP, 2>(C, witems, wmap, (const T *)Lx, wg[2], wg[3], r0, nr, w);
@@ -1420,7 +1424,7 @@ __global__ __launch_bounds__(NT, 3) void k_external(const Task *__restrict__ tas
     }
     if (ttime && blockIdx.y == 0) {
         __syncthreads();                    // every wavefront's work is issued
-        if (threadIdx.x == 0) ttime[blockIdx.x] = wall_clock64() - t_start;
+        if (threadIdx.x == 0) ttime[tq] = wall_clock64() - t_start;
     }
 }
 
@@ -1939,7 +1943,9 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
     int32_t chain = 0;
     for (const Phase &ph : P.phases) {
         const dim3 g((unsigned)(ph.t1 - ph.t0), m);
-        Bracket b(prof, s, (ph.kind == kPhaseExternal || ph.kind == kPhaseLeaf) ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
+        // profile kinds: external updates; off-diagonal solves; the
+        // factorizations inside supernodes (internal steps, leaves)
+        Bracket b(prof, s, ph.kind == kPhaseExternal ? 1 : ph.kind == kPhaseTrsm ? 2 : 3);
         if (ph.kind == kPhaseChain) {
             const int64_t nt = ph.t1 - ph.t0;
             const unsigned gx = (unsigned)std::min<int64_t>(nt, std::max(16, kChainGrid / (int)m));
@@ -1949,21 +1955,19 @@ hipError_t factor_impl(const Plan &P, const DevicePlan &D, const double *Ax, hip
             ++chain;
             continue;
         }
-        const int64_t nt = ph.t1 - ph.t0;
-        const int64_t nwide = ph.nwide < 0 ? nt : ph.nwide;
-        const dim3 gx((unsigned)(nwide + (nt - nwide + 3) / 4), m);
+        const dim3 gx((unsigned)ph.nslots, m);
         if (ph.kind == kPhaseExternal && P.phase_coop[&ph - P.phases.data()])
             k_external<T, true, OP><<<gx, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                      D.incs, D.imap, D.wptr + 16 * ph.t0, D.witems,
                                                      D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                      D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
-                                                     pfloor, P.n, D.cptr + ph.t0, D.chunks, nwide, nt);
+                                                     pfloor, P.n, D.cptr + ph.t0, D.chunks, D.xslot + ph.s0);
         else if (ph.kind == kPhaseExternal)
             k_external<T, false, OP><<<gx, NT, 0, s>>>(D.tasks + ph.t0, D.iptr + ph.t0, D.ibig + ph.t0,
                                                       D.incs, D.imap, D.wptr + 16 * ph.t0, D.witems,
                                                       D.wmap, D.blk, Lx, D.info, lxs, ttime(ph), D.parts,
                                                       D.pcount, (T *)D.pbuf, P.nsplit, P.npartial,
-                                                      pfloor, P.n, D.cptr + ph.t0, D.chunks, nwide, nt);
+                                                      pfloor, P.n, D.cptr + ph.t0, D.chunks, D.xslot + ph.s0);
         else if (ph.kind == kPhaseLeaf)
             k_leaf<T, OP != kOpNative><<<g, 64, 0, s>>>(D.tasks + ph.t0, D.blk, Lx, D.info, lxs, pfloor, P.n);
         else if (ph.kind == kPhaseInternal)

@@ -14,6 +14,7 @@
 // never the factor.
 #pragma once
 
+#include <climits>
 #include <cstdint>
 #include <vector>
 
@@ -101,6 +102,8 @@ static_assert(sizeof(StageChunk) == 32, "StageChunk layout is shared with the de
 static_assert(sizeof(WaveItem) == 32, "WaveItem layout is shared with the device");
 static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout is shared with the device");
 
+constexpr int32_t kQuadSlot = INT32_MIN;   // Plan::xslot: a slot of narrow tiles
+
 constexpr int32_t kFuseFactor = 1;
 // An internal update (kPhaseInternal) reads the source blocks K, K + 1, ...,
 // K + (flags >> kDepthShift) of the target's supernode, one product of inner
@@ -154,15 +157,16 @@ constexpr int kSuperFeatures = 12;  // features of a device supernode, see Plan:
 // followed by a kPhaseTrsm launch.
 // A kPhaseLeaf launch factors leaves of the supernodal tree whose block is
 // one tile of at most 16 columns (no update reaches a leaf), one wavefront
-// per block.  An external launch's tasks from Phase::nwide on are tiles of
-// blocks of at most 16 columns (not split, not staged), four to a
-// workgroup, one wavefront each.
+// per block.  An external launch runs its tasks by workgroup slot
+// (Plan::xslot): one task, or (kQuadSlot) up to four tiles of blocks of at
+// most 16 columns (not split, not staged), one wavefront each.
 enum PhaseKind : int32_t { kPhaseExternal = 0, kPhaseTrsm = 1, kPhaseInternal = 2, kPhaseChain = 3,
                            kPhaseLeaf = 4 };
 struct Phase {
     int32_t kind;
     int64_t t0, t1;     // task range in Plan::ftasks
-    int64_t nwide = -1; // kPhaseExternal: tasks of whole workgroups (the rest: one wavefront each); -1 = all
+    int64_t s0 = -1;    // kPhaseExternal: its workgroup slots at Plan::xslot[s0 .. s0 + nslots]
+    int64_t nslots = 0;
 };
 
 // Factor precisions (sym.h: SYM_F64, SYM_F32, SYM_BF16, SYM_F16).  FP32
@@ -322,6 +326,9 @@ struct Plan {
     // the tile's supernode (b0 + 1 for tile 0 of block b0, factored by the
     // external launch), becomes K + 1 once block K's update has been
     // applied, and J + 1 once the tile is final (factored or solved).
+    // per external launch: its slots' first tasks (launch-relative; bit 31
+    // marks a slot of narrow tiles), then its task count
+    std::vector<int32_t> xslot;
     std::vector<int32_t> tbase;     // nb + 1
     std::vector<int32_t> tinit;     // tbase[nb]: initial states
     int32_t nchain = 0;             // chain launches

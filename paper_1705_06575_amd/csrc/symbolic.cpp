@@ -218,7 +218,10 @@ void build_schedule(Plan &P)
     auto open_phase = [&](int32_t kind) { P.phases.push_back(Phase{kind, (int64_t)P.ftasks.size(), 0}); };
     auto close_phase = [&]() {
         P.phases.back().t1 = (int64_t)P.ftasks.size();
-        if (P.phases.back().t1 == P.phases.back().t0) P.phases.pop_back();
+        if (P.phases.back().t1 == P.phases.back().t0) {
+            if (P.phases.back().s0 >= 0) P.xslot.resize((size_t)P.phases.back().s0);
+            P.phases.pop_back();
+        }
     };
     // record one incidence of tile t of block J, with its relative indices
     auto emit_inc = [&](int32_t J, int32_t t, const RawInc &ri) {
@@ -362,6 +365,7 @@ void build_schedule(Plan &P)
     };
     std::vector<Pending> pending;
     std::vector<int32_t> leaves;
+    P.xslot.clear();
     for (int32_t l = 0; l < P.nslevels; ++l) {
         int32_t maxnb = 0;
         pending.clear();
@@ -428,8 +432,7 @@ void build_schedule(Plan &P)
         // tiles of blocks of at most 16 columns that are neither split nor
         // staged go to the level's one-wavefront launch (their products are
         // all per-wavefront items of the first wavefront)
-        std::vector<const Pending *> narrow;
-        auto emit_pending = [&](const Pending &pd, bool narrow_pass) {
+        auto cut_of = [&](const Pending &pd) {
             int32_t np = 1;
             if (pd.cost > unit)
                 np = std::min<int32_t>((int32_t)std::ceil(pd.cost / unit), (int32_t)pd.incs.size());
@@ -441,13 +444,12 @@ void build_schedule(Plan &P)
                     acc += (pd.incs[i].wk + 15) / 16;
                     if (acc >= share * (double)cut.size() && i + 1 < pd.incs.size()) cut.push_back(i + 1);
                 }
-                np = (int32_t)cut.size();
             }
             cut.push_back(pd.incs.size());
-            if (!narrow_pass && np == 1 && P.blk[pd.J].w <= 16 && P.svariant[pd.s2] != kVariantStaged) {
-                narrow.push_back(&pd);
-                return;
-            }
+            return cut;
+        };
+        auto emit_pending = [&](const Pending &pd, const std::vector<size_t> &cut) {
+            const int32_t np = (int32_t)cut.size() - 1;
             const int32_t counter = np > 1 ? lv_counters++ : -1;
             const int64_t slot0 = lv_slots;
             if (np > 1) lv_slots += np;
@@ -495,9 +497,63 @@ void build_schedule(Plan &P)
                     }
             }
         };
-        for (const Pending &pd : pending) emit_pending(pd, false);
-        P.phases.back().nwide = (int64_t)P.ftasks.size() - P.phases.back().t0;
-        for (const Pending *pd : narrow) emit_pending(*pd, true);
+        // Workgroup slots of the launch, longest first: a tile of its own,
+        // or up to four tiles of blocks of at most 16 columns that are
+        // neither split nor staged, one per wavefront (a narrow tile's
+        // products all belong to the first wavefront's columns, so a whole
+        // workgroup would idle three of its four); a slot of narrow tiles
+        // takes the next ones in the launch's order.
+        {
+            const size_t np = pending.size();
+            std::vector<std::vector<size_t>> cuts(np);
+            std::vector<uint8_t> nar(np, 0), done(np, 0);
+            for (size_t i = 0; i < np; ++i) {
+                cuts[i] = cut_of(pending[i]);
+                nar[i] = cuts[i].size() == 2 && P.blk[pending[i].J].w <= 16 &&
+                         P.svariant[pending[i].s2] != kVariantStaged;
+            }
+            const int64_t t0 = P.phases.back().t0;
+            P.phases.back().s0 = (int64_t)P.xslot.size();
+            size_t pn = 0;
+            for (size_t i = 0; i < np; ++i) {
+                if (done[i]) continue;
+                const int32_t first = (int32_t)((int64_t)P.ftasks.size() - t0);
+                if (!nar[i]) {
+                    // a slot per part of a split tile
+                    emit_pending(pending[i], cuts[i]);
+                    for (int32_t k = first; k < (int32_t)((int64_t)P.ftasks.size() - t0); ++k) P.xslot.push_back(k);
+                    done[i] = 1;
+                    continue;
+                }
+                P.xslot.push_back(first | kQuadSlot);
+                emit_pending(pending[i], cuts[i]);
+                done[i] = 1;
+                int32_t taken = 1;
+                pn = std::max(pn, i + 1);
+                for (; pn < np && taken < 4; ++pn) {
+                    if (!nar[pn] || done[pn]) continue;
+                    emit_pending(pending[pn], cuts[pn]);
+                    done[pn] = 1;
+                    ++taken;
+                }
+            }
+            P.phases.back().nslots = (int64_t)P.xslot.size() - P.phases.back().s0;
+            P.xslot.push_back((int32_t)((int64_t)P.ftasks.size() - t0));
+            // the slots cover the launch's tasks in order; a narrow slot
+            // holds one to four single-part tiles of at most 16 columns
+            const int64_t s0 = P.phases.back().s0, ns = P.phases.back().nslots;
+            for (int64_t k = 0; k < ns; ++k) {
+                const int32_t a = P.xslot[s0 + k] & INT32_MAX, b = P.xslot[s0 + k + 1] & INT32_MAX;
+                const bool quad = P.xslot[s0 + k] < 0;
+                if (b <= a || (!quad && b - a != 1) || b - a > 4) throw std::logic_error("launch slots");
+                if (quad)
+                    for (int32_t q = a; q < b; ++q) {
+                        const Task &tk = P.ftasks[t0 + q];
+                        if (P.blk[tk.J].w > 16 || (tk.flags & (kPartial | kStaged))) throw std::logic_error("launch slots");
+                    }
+            }
+            if (ns > 0 && (P.xslot[s0] & INT32_MAX) != 0) throw std::logic_error("launch slots");
+        }
         close_phase();
         if (!leaves.empty()) {
             open_phase(kPhaseLeaf);
