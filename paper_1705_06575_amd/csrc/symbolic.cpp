@@ -572,29 +572,34 @@ void build_schedule(Plan &P)
         close_phase();
         // Right-looking steps in groups of G blocks (local block indices):
         // step k with k % G != 0 updates the blocks of k's group from k on by
-        // block k - 1; step k with k % G == 0 updates every block from k on
-        // by the whole group [k - G, k), one product per tile.  Either way
-        // block k has then been updated by every block before it.
+        // block k - 1, and the diagonal tile of the next group's first block
+        // too; step k with k % G == 0 updates every block from k on by the
+        // whole group [k - G, k), one product per tile, except its own
+        // diagonal tile, which then lacks only block k - 1 (so the
+        // factorization every step waits for multiplies one block, not G).
+        // Either way block k has then been updated by every block before it.
         const int32_t G = std::max(1, P.update_depth);
         for (int32_t k = 1; k < maxnb; ++k) {
             open_phase(kPhaseInternal);
             const bool group_end = k % G == 0;
             const int32_t ksrc = group_end ? k - G : k - 1;
             const int32_t dflags = group_end ? (G - 1) << kDepthShift : 0;
+            const int32_t gnext = (k / G + 1) * G;     // the next group's first block
             // the tiles fused with a factorization (the longest) lead the launch
             for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
                 const int32_t s2 = sl_list[q];
                 const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
-                if (nbs > k) push_task(b0 + k, 0, b0 + ksrc, kFuseFactor | dflags, 0);
+                if (nbs > k) push_task(b0 + k, 0, b0 + k - 1, kFuseFactor, 0);
             }
             for (int32_t q = sl_ptr[l]; q < sl_ptr[l + 1]; ++q) {
                 const int32_t s2 = sl_list[q];
                 const int32_t b0 = P.sbptr[s2], nbs = P.sbptr[s2 + 1] - b0;
                 if (nbs <= k) continue;
-                const int32_t cend = group_end ? nbs : std::min(nbs, (k / G + 1) * G);
+                const int32_t cend = group_end ? nbs : std::min(nbs, gnext);
                 for (int32_t c = k; c < cend; ++c)
                     for (int32_t t = (c == k ? 1 : 0); t < ntiles(b0 + c); ++t)
                         push_task(b0 + c, t, b0 + ksrc, dflags, 0);
+                if (!group_end && gnext < nbs) push_task(b0 + gnext, 0, b0 + k - 1, 0, 0);
             }
             close_phase();
             open_phase(kPhaseTrsm);
