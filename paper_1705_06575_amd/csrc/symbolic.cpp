@@ -153,11 +153,28 @@ void build_schedule(Plan &P)
     // then 1; list order within a group), so the kernel runs each group
     // with loads and products for exactly that many row blocks; wptr holds
     // 16 boundaries per task (wavefront v, group g: entry 4 v + g).
+    // Within a group, items that meet more wavefronts come first (then by
+    // the set of wavefronts they meet, then list order): the four
+    // wavefronts start on the same products and meet their shared ones in
+    // the same order, so a product's rows, read once per wavefront, are
+    // read at nearly the same time and the later reads hit the cache.
     std::vector<WaveItem> wgroup[4];
+    std::vector<std::pair<int32_t, int32_t>> worder;
     auto emit_wave_items = [&](int32_t J, int32_t t, const std::vector<const RawInc *> &small) {
+        worder.clear();
+        for (int32_t i = 0; i < (int32_t)small.size(); ++i) {
+            relative(J, t, *small[i]);
+            int32_t mask = 0;
+            for (uint8_t c : crel) mask |= 1 << (c / 16);
+            const int32_t met = __builtin_popcount(mask);
+            worder.emplace_back(((4 - met) << 4) | mask, i);
+        }
+        std::stable_sort(worder.begin(), worder.end(),
+                         [](const auto &x, const auto &y) { return x.first < y.first; });
         for (int32_t v = 0; v < 4; ++v) {
             for (auto &g : wgroup) g.clear();
-            for (const RawInc *ri : small) {
+            for (const auto &wo : worder) {
+                const RawInc *ri = small[wo.second];
                 relative(J, t, *ri);
                 // columns are increasing: the wavefront's are a contiguous run
                 int32_t jlo = 0, jhi = 0;
