@@ -10,7 +10,7 @@ share, then the share for the winner.  Each candidate is analysed, bound
 and its factorization timed on the GPU (HIP events on the current stream,
 median of `reps` runs after one warm-up), for one value set or a whole
 batch.  The fastest candidate wins; the full table is returned so that a
-caller (or a learned model) can be judged against it.
+caller (or a learned model) can be measured against it.
 """
 from __future__ import annotations
 

@@ -28,7 +28,7 @@ supernodes with fewer update flops than the smallest training supernode
 keep the default; a variant replaces the default only when its predicted
 gain exceeds a margin chosen by leave-one-pattern-out validation on the
 training patterns (no replacement at all when no margin pays there).
-Exhaustive measurement of all variants stays the fallback and the judge:
+Exhaustive measurement of all variants stays the fallback and the yardstick:
 `regret` compares a choice with the per-supernode best.  A trained model
 is saved to and loaded from an .npz file (`Ensemble.save`, `load`); the
 package ships one trained on the k-NN family (`DEFAULT_MODEL`, written by

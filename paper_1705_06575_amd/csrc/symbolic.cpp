@@ -150,7 +150,7 @@ void build_schedule(Plan &P)
     };
     // the wavefront items of one task's small incidences, wavefront-major
     // Each wavefront's items are grouped by their 16-row blocks (4, 3, 2,
-    // then 1; list order within a group), so the kernel runs each group
+    // then 1), so the kernel runs each group
     // with loads and products for exactly that many row blocks; wptr holds
     // 16 boundaries per task (wavefront v, group g: entry 4 v + g).
     // Within a group, items that meet more wavefronts come first (then by
