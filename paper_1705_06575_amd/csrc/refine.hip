@@ -56,6 +56,8 @@ __global__ void k_red_reset(double *red)
 // G blockIdx.y ...), so the row's pattern (positions and columns) is read
 // once for all G; each instance's sum runs over the row in the same order
 // as with G = 1.
+constexpr int kRun = 4;
+
 template <int G>
 __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col,
@@ -74,16 +76,37 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
         double s[G], sa[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) s[g] = sa[g] = 0.0;
-        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            const int64_t v = val[p];
-            const int32_t c = col[p];
+        // the row's entries in runs of kRun: all loads of a run are issued
+        // before its products (addresses clamped into the row), which are
+        // then taken in entry order
+        const int64_t pb = rowptr[i], pe = rowptr[i + 1];
+        for (int64_t p0 = pb; p0 < pe; p0 += kRun) {
+            int64_t v[kRun];
+            int32_t c[kRun];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int64_t gi = min(g0 + g, m - 1);
-                const double a = Ax[gi * nnzA + v];
-                s[g] += a * x[gi * n + c];
-                sa[g] += fabs(a);
+            for (int u = 0; u < kRun; ++u) {
+                const int64_t p = min(p0 + u, pe - 1);
+                v[u] = val[p];
+                c[u] = col[p];
             }
+            double a[kRun][G], xv[kRun][G];
+#pragma unroll
+            for (int u = 0; u < kRun; ++u)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int64_t gi = min(g0 + g, m - 1);
+                    a[u][g] = Ax[gi * nnzA + v[u]];
+                    xv[u][g] = x[gi * n + c[u]];
+                }
+#pragma unroll
+            for (int u = 0; u < kRun; ++u)
+                if (p0 + u < pe) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        s[g] += a[u][g] * xv[u][g];
+                        sa[g] += fabs(a[u][g]);
+                    }
+                }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -119,7 +142,8 @@ __global__ void k_axpy(double *__restrict__ x, const double *__restrict__ d, int
         x[i] += d[i];
 }
 
-// q = A p over the full symmetric rows, one thread per row.
+// q = A p over the full symmetric rows, one thread per row (entries in
+// runs of kRun, loads before products, products in entry order).
 __global__ __launch_bounds__(256) void k_spmv(const int64_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ col,
                                               const int64_t *__restrict__ val,
@@ -129,7 +153,19 @@ __global__ __launch_bounds__(256) void k_spmv(const int64_t *__restrict__ rowptr
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) s += Ax[val[k]] * p[col[k]];
+        const int64_t kb = rowptr[i], ke = rowptr[i + 1];
+        for (int64_t k0 = kb; k0 < ke; k0 += kRun) {
+            double a[kRun], pv[kRun];
+#pragma unroll
+            for (int u = 0; u < kRun; ++u) {
+                const int64_t k = min(k0 + u, ke - 1);
+                a[u] = Ax[val[k]];
+                pv[u] = p[col[k]];
+            }
+#pragma unroll
+            for (int u = 0; u < kRun; ++u)
+                if (k0 + u < ke) s += a[u] * pv[u];
+        }
         q[i] = s;
     }
 }
