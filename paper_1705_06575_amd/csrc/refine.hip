@@ -56,7 +56,7 @@ __global__ void k_red_reset(double *red)
 // G blockIdx.y ...), so the row's pattern (positions and columns) is read
 // once for all G; each instance's sum runs over the row in the same order
 // as with G = 1.
-constexpr int kRun = 4;
+constexpr int kRun = 8;
 
 template <int G>
 __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ rowptr,
@@ -76,22 +76,24 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
         double s[G], sa[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) s[g] = sa[g] = 0.0;
-        // the row's entries in runs of kRun: all loads of a run are issued
-        // before its products (addresses clamped into the row), which are
-        // then taken in entry order
+        // the row's entries in runs (kRun for one value set, four when the
+        // thread holds four value sets): all loads of a run
+        // are issued before its products (addresses clamped into the row),
+        // which are then taken in entry order
         const int64_t pb = rowptr[i], pe = rowptr[i + 1];
-        for (int64_t p0 = pb; p0 < pe; p0 += kRun) {
-            int64_t v[kRun];
-            int32_t c[kRun];
+        constexpr int R = G == 1 ? kRun : 4;
+        for (int64_t p0 = pb; p0 < pe; p0 += R) {
+            int64_t v[R];
+            int32_t c[R];
 #pragma unroll
-            for (int u = 0; u < kRun; ++u) {
+            for (int u = 0; u < R; ++u) {
                 const int64_t p = min(p0 + u, pe - 1);
                 v[u] = val[p];
                 c[u] = col[p];
             }
-            double a[kRun][G], xv[kRun][G];
+            double a[R][G], xv[R][G];
 #pragma unroll
-            for (int u = 0; u < kRun; ++u)
+            for (int u = 0; u < R; ++u)
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     const int64_t gi = min(g0 + g, m - 1);
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t *__restrict__ ro
                     xv[u][g] = x[gi * n + c[u]];
                 }
 #pragma unroll
-            for (int u = 0; u < kRun; ++u)
+            for (int u = 0; u < R; ++u)
                 if (p0 + u < pe) {
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
